@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of direct inverse ray-shooting on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic map: the ray grid
+is generated on the device, every ray is deflected by direct summation over all
+lenses, mapped through the lens equation and binned (rs_shoot).  Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  The flop convention is the paper's: 10 flop per
+ray-lens interaction (Thompson et al. 2009, appendix A).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ray·lens interactions/s & Gflop/s; rays/s surrogate vs direct at ≤1% map err"
+FLOP_PER_INTERACTION = 10
+PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak (packed FMA)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paper", choices=["paper", "small"])
+    ap.add_argument("--rays-per-lane", type=int, default=0)
+    ap.add_argument("--lens-tile", type=int, default=0)
+    ap.add_argument("--fp32-run", type=int, default=0)
+    ap.add_argument("--map-window", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    return ap.parse_args()
+
+
+def workload(name):
+    import synth
+    if name == "small":
+        return synth.workload_small()
+    return synth.workload_paper()
+
+
+def cpu_baseline(w, target_cpu_s: float):
+    """The FP64 oracle on a bounded sample of the same workload (rays drawn with the counter hash)."""
+    import oracle
+    import synth
+    threads = max(1, min(16, os.cpu_count() or 1))
+    # calibrate on a tiny sample, then size the real one to ~target_cpu_s of CPU time
+    probe = synth.sample_indices(99, w.n_rays, 256)
+    t0 = time.perf_counter()
+    oracle.trace(w, probe)
+    per_ray = max(1e-7, (time.perf_counter() - t0) / len(probe))
+    n = int(min(w.n_rays, max(threads, target_cpu_s / per_ray)))
+    idx = synth.sample_indices(100, w.n_rays, n)
+    t0 = time.perf_counter()
+    oracle.trace_parallel(w, idx, threads=threads)
+    dt = time.perf_counter() - t0
+    inter = len(idx) * w.n_lens
+    return {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} rays drawn by counter hash from the {w.name} grid x all {w.n_lens} lenses, "
+                      f"FP64 single-threaded oracle on {threads} threads, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in the design notes but not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0905_2453_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = workload(args.workload)
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    opts = P.Opts()
+    opts.rays_per_lane, opts.lens_tile = args.rays_per_lane, args.lens_tile
+    opts.fp32_run, opts.map_window = args.fp32_run, args.map_window
+    job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                     counts, lost)
+    ws = torch.empty(P.workspace_bytes(job, opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        counts.zero_()
+        lost.zero_()
+        P.shoot_job(job, ws, opts, stream)
+    torch.cuda.synchronize()
+    counts.zero_()
+    lost.zero_()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        P.shoot_job(job, ws, opts, stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_step = 1e3 * wall / args.steps
+    inter = float(w.n_rays) * float(w.n_lens)
+    value = inter * args.steps / wall
+    kernel_s = float(np.mean(launch_ms)) * 1e-3
+    achieved_tf = FLOP_PER_INTERACTION * inter / kernel_s / 1e12
+    total = int(counts.sum().item()) + int(lost.item())
+    if total != w.n_rays * args.steps:
+        print(f"bench.py: ray conservation failed ({total} != {w.n_rays * args.steps})", file=sys.stderr)
+        sys.exit(3)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_lens": w.n_lens, "ray_grid": list(w.grid_n),
+                   "map": list(w.map_n), "kappa_star": w.kappa_star, "kappa_c": w.kappa_c, "gamma": w.gamma,
+                   "masses": "unit" if args.workload == "small" else "power law 2.35 on [0.1,1]",
+                   "fp64_combine": True, "parallelism": "1 GPU"},
+        "gflops": value * FLOP_PER_INTERACTION / 1e9,
+        "rays_per_s": w.n_rays * args.steps / wall,
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_direct", "flop_per_interaction": FLOP_PER_INTERACTION,
+                     "kernel_ms": kernel_s * 1e3,
+                     "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

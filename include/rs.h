@@ -1,0 +1,147 @@
+/*
+ * rs.h -- C ABI of librs, an MI355X (gfx950) inverse ray-shooting library.
+ *
+ * The method is direct inverse ray-shooting for microlensing magnification
+ * maps (Thompson, Fluke, Barnes & Barsdell 2009):
+ *   lens equation                y = x - alpha(x)                 (section 1, eq. 1)
+ *   many-Schwarzschild deflection alpha(x) = sum_i m_i (x - x_i) / |x - x_i|^2
+ *                                                                  (section 1, eq. 2)
+ *   direct sum split into lens subsets whose partial sums are added
+ *                                                                  (section 2, eq. 5)
+ *   macro model  y = diag(1-gamma, 1+gamma) x - kappa_c x - alpha  (section 3.2, eq. 6)
+ *   estimator    mu_ij = N_ij / N_av, N_ij = rays in pixel (i, j)  (section 1, eq. 4)
+ *
+ * Conventions shared by every entry point
+ *   - Lengths are in Einstein radii of a unit-mass lens.
+ *   - Rays sit at the centres of a regular grid: coordinate i of axis k is the
+ *     float32 rounding of lo_k + (i + 1/2) (hi_k - lo_k) / n_k, evaluated in
+ *     FP64 as t = (hi-lo)/n, v = (i + 0.5) t, w = lo + v (no fused operations).
+ *   - The deflection is summed in float32 over runs of consecutive lenses
+ *     (lens-index order); each run's partial sum is added to a per-ray FP64
+ *     accumulator (eq. 5 with FP64 combination).  The lens equation and the
+ *     pixel index are evaluated in FP64.
+ *   - Source pixels are half-open: p_k = floor((y_k - lo_k) * (n_k / (hi_k - lo_k))).
+ *     A ray is counted iff y is finite and 0 <= p_k < n_k; otherwise it is
+ *     "lost" (this includes a ray exactly on a lens).
+ *   - Maps are uint32, row-major with axis 1 fastest: counts[p2 * n1 + p1].
+ *     Every call ADDS into counts and n_lost; the caller zeroes them.
+ *
+ * Ownership and memory
+ *   - Every pointer marked "device" is device memory owned by the caller.
+ *     The library never allocates device memory: workspace sizes come from
+ *     the *_bytes queries and the caller passes the buffers in.
+ *   - Host structs are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued asynchronously; kernel faults surface on the caller's next
+ *     synchronisation.  Calls that share a workspace must be ordered.
+ *
+ * Errors
+ *   Every function returns rs_status and never aborts, throws or prints.
+ *   Invalid arguments are rejected before any HIP call.  rs_last_error()
+ *   returns a thread-local description of the last failure on this thread.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RS_OK = 0,
+    RS_EINVAL = -1,     /* invalid argument (NULL, negative or empty size, bad region, ...)  */
+    RS_ERANGE = -2,     /* a size exceeds what one call supports (e.g. >= 2^31 rays)         */
+    RS_EDEVICE = -3,    /* a HIP launch or runtime call failed (text in rs_last_error)       */
+    RS_ESMALLBUF = -4,  /* workspace or model buffer smaller than its *_bytes query          */
+    RS_ENOTFIT = -5,    /* a far-field model does not match the job / configuration          */
+    RS_EINTERNAL = -6   /* unexpected internal state                                         */
+} rs_status;
+
+/* Human-readable name of a status code (static string). */
+const char *rs_status_str(int status);
+/* Thread-local detail of the last failure on the calling thread (static until the next call). */
+const char *rs_last_error(void);
+/* Library version string. */
+const char *rs_version(void);
+
+/* One point lens: position (x1, x2) and mass m (eq. 2); pad is ignored.  16 bytes. */
+typedef struct {
+    float x1, x2, m, pad;
+} rs_lens;
+
+/* Macro model of eq. 6: smooth convergence kappa_c (the paper's sigma_c) and external shear. */
+typedef struct {
+    double kappa_c, gamma;
+} rs_macro;
+
+/*
+ * Image-plane ray grid: the rectangle [lo, hi) cut into n[0] x n[1] cells, one
+ * ray per cell centre.  Only the window [win_lo, win_lo + win_n) is shot by a
+ * call, so a large grid can be streamed in pieces whose ray positions do not
+ * depend on the split.
+ */
+typedef struct {
+    double lo[2], hi[2];
+    int64_t n[2];
+    int64_t win_lo[2], win_n[2];
+} rs_raygrid;
+
+/* Source-plane map: the rectangle [lo, hi) cut into n[0] x n[1] half-open pixels. */
+typedef struct {
+    double lo[2], hi[2];
+    int32_t n[2];
+} rs_map;
+
+/* One magnification-map job. */
+typedef struct {
+    const rs_lens *lenses;   /* device, n_lens records                                       */
+    int64_t n_lens;          /* >= 0                                                         */
+    rs_macro macro;
+    rs_raygrid grid;
+    rs_map map;
+    uint32_t *counts;        /* device, map.n[1] * map.n[0], ACCUMULATED (+=)                */
+    uint64_t *n_lost;        /* device, one counter, ACCUMULATED (+=)                        */
+} rs_job;
+
+/* Flags for rs_opts.flags */
+#define RS_FLAG_FAULT_INJECT 0x1u  /* fail with RS_EDEVICE after validation, before any HIP call */
+
+/*
+ * Tuning and diagnostics for rs_shoot.  NULL, or a zero field, selects the
+ * default.  Results depend on fp32_run only (the length of the float32 runs
+ * before each FP64 addition); the other fields change speed, not values.
+ */
+typedef struct {
+    int32_t rays_per_lane;   /* rays held in registers per lane: 4, 8 or 16 (default 4)        */
+    int32_t lens_tile;       /* lenses staged in LDS per tile: 256 or 512 (default 256)        */
+    int32_t fp32_run;        /* lenses per float32 run: 8, 16 or 32 (default 16)               */
+    int32_t map_window;      /* side of the LDS-privatised map window: 16, 32 or 64; -1 = off */
+    double *ray_y;           /* optional device output, 2 doubles per ray of the window        */
+    int32_t *ray_pix;        /* optional device output, pixel p2*n1+p1 per ray, -1 = lost      */
+    uint32_t flags;          /* RS_FLAG_*                                                      */
+} rs_opts;
+
+/*
+ * Workspace bytes rs_shoot needs for this job (8 partial maps, one per
+ * accelerator complex die, plus alignment).  Returns 0 for an invalid job.
+ */
+size_t rs_workspace_bytes(const rs_job *job, const rs_opts *opts);
+
+/*
+ * Shoot the job's ray window and add its counts to job->counts and job->n_lost.
+ * Direct inverse ray-shooting (eqs. 1, 2, 4, 5, 6).
+ *   workspace: device, >= rs_workspace_bytes(job, opts) bytes, contents ignored
+ *   (overwritten).  opts may be NULL.
+ * Returns RS_EINVAL / RS_ERANGE / RS_ESMALLBUF before any HIP call on bad
+ * arguments, RS_EDEVICE if a launch fails.  An empty window is a no-op.
+ */
+int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_H */

@@ -1,0 +1,134 @@
+"""Python binding of librs: MI355X inverse ray-shooting (Thompson et al. 2009).
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+kernels of ``librs.so`` behind the C ABI declared in ``include/rs.h``; torch
+supplies device memory and streams.  If the library is missing the binding
+raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import _abi
+from ._abi import RayShootError, Opts  # noqa: F401
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librs.so")
+
+_lib = None
+
+
+def lib():
+    """The loaded librs.so (raises RuntimeError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0905_2453_amd.build.build()")
+        _lib = _abi.bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(st: int):
+    if st != 0:
+        L = lib()
+        raise RayShootError(st, L.rs_status_str(st).decode(), L.rs_last_error().decode())
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts, lost,
+             window=None) -> _abi.Job:
+    """Fill an rs_job from device tensors and plain numbers (no copies)."""
+    torch = _torch()
+    _require_cuda(lenses, "lenses", torch.float32)
+    if lenses.dim() != 2 or lenses.shape[1] != 4:
+        raise ValueError("lenses must be an n x 4 float32 tensor (x1, x2, m, 0)")
+    _require_cuda(counts, "counts", torch.int32)
+    _require_cuda(lost, "lost", torch.int64)
+    if counts.numel() != int(map_n[0]) * int(map_n[1]):
+        raise ValueError("counts must hold map_n[1] * map_n[0] bins")
+    if window is None:
+        window = ((0, 0), (int(grid_n[0]), int(grid_n[1])))
+    j = _abi.Job()
+    j.lenses = ctypes.c_void_p(lenses.data_ptr() if lenses.shape[0] else 0)
+    j.n_lens = int(lenses.shape[0])
+    j.macro.kappa_c = float(kappa_c)
+    j.macro.gamma = float(gamma)
+    for k in range(2):
+        j.grid.lo[k] = float(grid_lo[k])
+        j.grid.hi[k] = float(grid_hi[k])
+        j.grid.n[k] = int(grid_n[k])
+        j.grid.win_lo[k] = int(window[0][k])
+        j.grid.win_n[k] = int(window[1][k])
+        j.map.lo[k] = float(map_lo[k])
+        j.map.hi[k] = float(map_hi[k])
+        j.map.n[k] = int(map_n[k])
+    j.counts = ctypes.c_void_p(counts.data_ptr())
+    j.n_lost = ctypes.c_void_p(lost.data_ptr())
+    return j
+
+
+def workspace_bytes(job: _abi.Job, opts: Opts | None = None) -> int:
+    n = lib().rs_workspace_bytes(ctypes.byref(job), ctypes.byref(opts) if opts else None)
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+def shoot_job(job: _abi.Job, workspace, opts: Opts | None = None, stream=None) -> None:
+    """rs_shoot on a filled job with a caller-owned workspace tensor (uint8/any dtype)."""
+    _require_cuda(workspace, "workspace")
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().rs_shoot(ctypes.byref(job), ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                          _stream_handle(stream), ctypes.byref(opts) if opts else None))
+
+
+def shoot(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts=None,
+          lost=None, window=None, opts: Opts | None = None, workspace=None, stream=None):
+    """Shoot a ray-grid window and add its counts into ``counts`` (int32 view of uint32 bins).
+
+    Returns (counts, lost): counts is map_n[1] x map_n[0], lost a 1-element int64 tensor.
+    Both accumulate when passed in.
+    """
+    torch = _torch()
+    dev = lenses.device
+    if counts is None:
+        counts = torch.zeros((int(map_n[1]), int(map_n[0])), dtype=torch.int32, device=dev)
+    if lost is None:
+        lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    job = make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts, lost,
+                   window)
+    if workspace is None:
+        workspace = torch.empty(workspace_bytes(job, opts), dtype=torch.uint8, device=dev)
+    shoot_job(job, workspace, opts, stream)
+    return counts, lost
+
+
+def shoot_workload(w, device="cuda", opts: Opts | None = None, window=None, lenses=None, stream=None):
+    """Convenience: shoot a ``synth.Workload``-like object (lenses uploaded unless given)."""
+    torch = _torch()
+    if lenses is None:
+        lenses = torch.from_numpy(w.lenses).to(device)
+    return shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                 window=window, opts=opts, stream=stream)

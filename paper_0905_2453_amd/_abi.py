@@ -1,0 +1,69 @@
+"""ctypes mirror of the structs and functions declared in include/rs.h."""
+from __future__ import annotations
+
+import ctypes
+
+c_double2 = ctypes.c_double * 2
+c_int64_2 = ctypes.c_int64 * 2
+c_int32_2 = ctypes.c_int32 * 2
+
+RS_OK = 0
+RS_EINVAL = -1
+RS_ERANGE = -2
+RS_EDEVICE = -3
+RS_ESMALLBUF = -4
+RS_ENOTFIT = -5
+RS_EINTERNAL = -6
+
+RS_FLAG_FAULT_INJECT = 0x1
+
+
+class RayShootError(RuntimeError):
+    def __init__(self, status: int, name: str, detail: str):
+        super().__init__(f"{name} ({status}): {detail}")
+        self.status = status
+        self.name = name
+        self.detail = detail
+
+
+class Macro(ctypes.Structure):
+    _fields_ = [("kappa_c", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class RayGrid(ctypes.Structure):
+    _fields_ = [("lo", c_double2), ("hi", c_double2), ("n", c_int64_2), ("win_lo", c_int64_2),
+                ("win_n", c_int64_2)]
+
+
+class Map(ctypes.Structure):
+    _fields_ = [("lo", c_double2), ("hi", c_double2), ("n", c_int32_2)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("lenses", ctypes.c_void_p), ("n_lens", ctypes.c_int64), ("macro", Macro),
+                ("grid", RayGrid), ("map", Map), ("counts", ctypes.c_void_p), ("n_lost", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("rays_per_lane", ctypes.c_int32), ("lens_tile", ctypes.c_int32), ("fp32_run", ctypes.c_int32),
+                ("map_window", ctypes.c_int32), ("ray_y", ctypes.c_void_p), ("ray_pix", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+# (name, restype, argtypes) of every exported function
+EXPORTS = [
+    ("rs_status_str", ctypes.c_char_p, [ctypes.c_int]),
+    ("rs_last_error", ctypes.c_char_p, []),
+    ("rs_version", ctypes.c_char_p, []),
+    ("rs_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(Opts)]),
+    ("rs_shoot", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                ctypes.POINTER(Opts)]),
+]
+
+
+def bind(L: ctypes.CDLL) -> ctypes.CDLL:
+    for name, res, args in EXPORTS:
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L

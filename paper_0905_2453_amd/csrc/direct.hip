@@ -1,0 +1,334 @@
+// Direct inverse ray-shooting on gfx950: FP32 VALU direct sum with LDS-staged lens tiles,
+// FP64 run combination, FP64 lens equation and LDS-privatised binning.
+//
+// Method: Thompson, Fluke, Barnes & Barsdell (2009), section 1 eqs. 1, 2, 4; section 2 eq. 5;
+// section 3.2 eq. 6; the 10-flop interaction of appendix A.
+//
+// Work decomposition.  A workgroup of 4 wave64s owns a tile of 64 grid columns x (4 K) grid
+// rows: lane l of wave w holds the K rays (column c0 + l, rows r0 + w K + k), k < K.  The K
+// rays of a lane share x1, so x1 - x1_i and its square are computed once per lens and each
+// ray-lens interaction costs a subtract, an FMA (r^2), a reciprocal, a multiply (m / r^2) and
+// two FMAs (alpha).  Lenses stream through LDS in tiles of LT records (double buffered); every
+// lane reads the same record, so each LDS read is a broadcast.  Partial sums run in float32
+// over T consecutive lenses, then are added to a per-ray FP64 accumulator.
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+
+// Coordinate i of a grid axis (cell centre), FP64 then rounded to float32.
+__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i)
+{
+    double v = ((double)i + 0.5) * t;
+    double w = lo + v;
+    return (float)w;
+}
+
+// Half-open source pixel of y; returns p2 * n1 + p1, or -1 when the ray is lost.
+__device__ __forceinline__ int pixel_of(double y1, double y2, const DirectArgs &a, int &p1, int &p2)
+{
+    double f1 = floor((y1 - a.mlo1) * a.ms1);
+    double f2 = floor((y2 - a.mlo2) * a.ms2);
+    if (!(f1 >= 0.0 && f1 < (double)a.mn1 && f2 >= 0.0 && f2 < (double)a.mn2)) return -1;
+    p1 = (int)f1;
+    p2 = (int)f2;
+    return p2 * a.mn1 + p1;
+}
+
+// 1 / (1 + mean relative error of v_rcp_f32), the error measured over every float32 mantissa
+// in [1, 2) with weight 1/x.
+constexpr double kRcpBiasComp = 1.0 + 6.41e-9;
+
+__device__ __forceinline__ float4 pad_lens()
+{
+    return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
+}
+
+template <int K, int T, int LT, bool DUMP>
+__global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
+{
+    static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
+    constexpr int PER = LT / kThreads;
+    __shared__ float4 s_lens[2][LT];
+    __shared__ uint32_t s_win[kMaxWindow * kMaxWindow];
+    __shared__ int s_cand[2][2 * kWaves];
+    __shared__ uint32_t s_lost;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int tx = (int)(blockIdx.x % (uint32_t)a.tiles_x);
+    const int ty = (int)(blockIdx.x / (uint32_t)a.tiles_x);
+    const int64_t c1 = (int64_t)tx * 64 + lane;
+    const int64_t r0 = (int64_t)ty * (kWaves * K) + (int64_t)wave * K;
+
+    const float x1 = ray_coord(a.glo1, a.gt1, a.wlo1 + c1);
+    float x2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) x2[k] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + k);
+
+    for (int b = tid; b < kMaxWindow * kMaxWindow; b += kThreads) s_win[b] = 0u;
+    if (tid == 0) s_lost = 0u;
+
+    double A1[K], A2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { A1[k] = 0.0; A2[k] = 0.0; }
+
+    const int64_t n_tiles = (a.n_lens + LT - 1) / LT;
+    float4 reg[PER];
+    if (n_tiles > 0) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            int64_t i = (int64_t)p * kThreads + tid;
+            reg[p] = i < a.n_lens ? a.lenses[i] : pad_lens();
+            s_lens[0][p * kThreads + tid] = reg[p];
+        }
+    }
+    __syncthreads();
+
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        const int buf = (int)(t & 1);
+        const bool more = t + 1 < n_tiles;
+        if (more) {
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                int64_t i = (t + 1) * LT + (int64_t)p * kThreads + tid;
+                reg[p] = i < a.n_lens ? a.lenses[i] : pad_lens();
+            }
+        }
+        const float4 *L = s_lens[buf];
+        for (int r = 0; r < LT; r += T) {
+            float s1[K], s2[K];
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                const float4 l = L[r + j];
+                const float dx = x1 - l.x;
+                const float dx2 = dx * dx;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float dy = x2[k] - l.y;
+                    const float r2 = fmaf(dy, dy, dx2);
+                    const float d = l.z * __builtin_amdgcn_rcpf(r2);
+                    if (j == 0) {
+                        s1[k] = d * dx;
+                        s2[k] = d * dy;
+                    } else {
+                        s1[k] = fmaf(d, dx, s1[k]);
+                        s2[k] = fmaf(d, dy, s2[k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                A1[k] += (double)s1[k];
+                A2[k] += (double)s2[k];
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int p = 0; p < PER; ++p) s_lens[buf ^ 1][p * kThreads + tid] = reg[p];
+        }
+        __syncthreads();
+    }
+
+    // The hardware reciprocal is biased low: over all float32 mantissas, weighted as for
+    // log-uniform arguments, its mean relative error is -6.41e-9.  Summed coherently over many
+    // lenses this bias would dominate the float32 error of large deflections, so the FP64 sum
+    // is rescaled by the inverse factor (two FP64 multiplies per ray, no per-lens cost).
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        A1[k] *= kRcpBiasComp;
+        A2[k] *= kRcpBiasComp;
+    }
+
+    // Lens equation (eq. 6) and source pixel, FP64.
+    const bool col_ok = c1 < a.wn1;
+    int key[K], q1[K], q2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool ok = col_ok && (r0 + k < a.wn2);
+        const double y1 = a.lam1 * (double)x1 - A1[k];
+        const double y2 = a.lam2 * (double)x2[k] - A2[k];
+        int p1 = 0, p2 = 0;
+        const int kv = pixel_of(y1, y2, a, p1, p2);
+        key[k] = ok ? kv : -2;
+        q1[k] = p1;
+        q2[k] = p2;
+        if (DUMP && ok) {
+            const int64_t ri = (r0 + k) * a.wn1 + c1;
+            a.ray_y[2 * ri] = y1;
+            a.ray_y[2 * ri + 1] = y2;
+            a.ray_pix[ri] = kv;
+        }
+    }
+
+    // Window origin: per-axis median of 8 sample rays of the tile (robust to rays scattered
+    // far by a close lens).
+    const int W = a.window;
+    int o1 = 0, o2 = 0;
+    if (W > 0) {
+        constexpr int ka = K / 4, kb = (3 * K) / 4;
+        if (lane == 16) {
+            s_cand[0][2 * wave] = key[ka] >= 0 ? q1[ka] : INT_MIN;
+            s_cand[1][2 * wave] = key[ka] >= 0 ? q2[ka] : INT_MIN;
+        }
+        if (lane == 48) {
+            s_cand[0][2 * wave + 1] = key[kb] >= 0 ? q1[kb] : INT_MIN;
+            s_cand[1][2 * wave + 1] = key[kb] >= 0 ? q2[kb] : INT_MIN;
+        }
+        __syncthreads();
+        int v1[2 * kWaves], v2[2 * kWaves], n = 0;
+#pragma unroll
+        for (int c = 0; c < 2 * kWaves; ++c) {
+            const int a1 = s_cand[0][c], a2 = s_cand[1][c];
+            if (a1 != INT_MIN) { v1[n] = a1; v2[n] = a2; ++n; }
+        }
+        if (n > 0) {
+            // insertion sorts of at most 8 values
+            for (int i = 1; i < n; ++i) {
+                int u = v1[i], w = v2[i], j = i - 1;
+                while (j >= 0 && v1[j] > u) { v1[j + 1] = v1[j]; --j; }
+                v1[j + 1] = u;
+                j = i - 1;
+                while (j >= 0 && v2[j] > w) { v2[j + 1] = v2[j]; --j; }
+                v2[j + 1] = w;
+            }
+            o1 = v1[n / 2] - W / 2;
+            o2 = v2[n / 2] - W / 2;
+        }
+    }
+
+    // Binning: runs of equal keys among consecutive lanes are added once (wave aggregation),
+    // into the LDS window when the pixel falls inside it, else into this die's partial map.
+    uint32_t *part = a.partial + (size_t)(blockIdx.x & (kPartials - 1)) * (size_t)a.pstride;
+    uint32_t lost_cnt = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int kv = key[k];
+        const int prev = __shfl_up(kv, 1);
+        const bool head = (lane == 0) || (kv != prev);
+        const unsigned long long H = __ballot(head);
+        const unsigned long long above = lane == 63 ? 0ull : (H >> (lane + 1));
+        const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
+        const uint32_t cnt = (uint32_t)(next - lane);
+        if (head) {
+            if (kv >= 0) {
+                const int w1 = q1[k] - o1, w2 = q2[k] - o2;
+                if (W > 0 && (unsigned)w1 < (unsigned)W && (unsigned)w2 < (unsigned)W)
+                    atomicAdd(&s_win[w2 * W + w1], cnt);
+                else
+                    atomicAdd(&part[kv], cnt);
+            } else if (kv == -1) {
+                lost_cnt += cnt;
+            }
+        }
+    }
+    if (lost_cnt) atomicAdd(&s_lost, lost_cnt);
+    __syncthreads();
+
+    // Flush the window's non-zero bins.
+    if (W > 0) {
+        for (int b = tid; b < W * W; b += kThreads) {
+            const uint32_t v = s_win[b];
+            if (v) atomicAdd(&part[(int64_t)(o2 + b / W) * a.mn1 + (o1 + b % W)], v);
+        }
+    }
+    if (tid == 0 && s_lost) atomicAdd(a.lost, (unsigned long long)s_lost);
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint4 *p, int64_t n4)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// counts[b] += sum over the kPartials maps; partial maps are kPartials x pstride words with
+// pstride a multiple of 64, so every group of four bins is 16-byte aligned in the workspace.
+__global__ void __launch_bounds__(256) k_reduce(const uint32_t *partial, int64_t bins, int64_t pstride,
+                                                 uint32_t *counts)
+{
+    const int64_t n4 = (bins + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const bool vec = ((uintptr_t)counts & 15u) == 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        uint4 s = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int p = 0; p < kPartials; ++p) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(partial + (size_t)p * pstride + 4 * i);
+            s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+        }
+        const int64_t b = 4 * i;
+        if (vec && b + 3 < bins) {
+            uint4 *c = reinterpret_cast<uint4 *>(counts + b);
+            uint4 o = *c;
+            o.x += s.x; o.y += s.y; o.z += s.z; o.w += s.w;
+            *c = o;
+        } else {
+            const uint32_t sv[4] = {s.x, s.y, s.z, s.w};
+            for (int j = 0; j < 4 && b + j < bins; ++j) counts[b + j] += sv[j];
+        }
+    }
+}
+
+template <int K, int T, int LT>
+hipError_t launch_kt(const DirectArgs &a, int64_t n_tiles, hipStream_t s)
+{
+    if (a.ray_y)
+        hipLaunchKernelGGL((k_direct<K, T, LT, true>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_direct<K, T, LT, false>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_k(const DirectArgs &a, int T, int LT, int64_t n_tiles, hipStream_t s)
+{
+    if (LT == 256) {
+        if (T == 8) return launch_kt<K, 8, 256>(a, n_tiles, s);
+        if (T == 16) return launch_kt<K, 16, 256>(a, n_tiles, s);
+        if (T == 32) return launch_kt<K, 32, 256>(a, n_tiles, s);
+    } else if (LT == 512) {
+        if (T == 8) return launch_kt<K, 8, 512>(a, n_tiles, s);
+        if (T == 16) return launch_kt<K, 16, 512>(a, n_tiles, s);
+        if (T == 32) return launch_kt<K, 32, 512>(a, n_tiles, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_direct(const DirectArgs &a, int K, int T, int LT, int64_t n_tiles, hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    switch (K) {
+    case 4: return launch_k<4>(a, T, LT, n_tiles, s);
+    case 8: return launch_k<8>(a, T, LT, n_tiles, s);
+    case 16: return launch_k<16>(a, T, LT, n_tiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s)
+{
+    const int64_t n4 = n_words / 4;
+    if (n4 <= 0) return hipSuccess;
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint4 *>(p), n4);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride, uint32_t *counts,
+                         hipStream_t s)
+{
+    const int64_t n4 = (bins + 3) / 4;
+    if (n4 <= 0) return hipSuccess;
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(256), 0, s, partial, bins, pstride, counts);
+    return hipGetLastError();
+}
+
+}  // namespace rs

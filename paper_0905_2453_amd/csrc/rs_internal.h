@@ -1,0 +1,47 @@
+// Internal declarations shared by the host runtime and the HIP kernels of librs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rs.h"
+
+namespace rs {
+
+// Rays of one workgroup tile: 64 grid columns (one per lane) x (WAVES * K) rows.
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxWindow = 64;          // LDS map window side (bins)
+constexpr int kPartials = 8;            // partial maps, one per accelerator complex die
+constexpr float kPadCoord = 1.0e18f;    // position of the zero-mass lenses padding a tile
+
+// Everything one direct-sum launch needs, already reduced to FP64 constants on the host.
+struct DirectArgs {
+    const float4 *lenses;   // n_lens records (x1, x2, m, pad)
+    int64_t n_lens;
+    double glo1, glo2;      // grid lower corner
+    double gt1, gt2;        // grid cell size (hi - lo) / n, computed on the host in FP64
+    int64_t wlo1, wlo2;     // ray window origin (grid indices)
+    int64_t wn1, wn2;       // ray window size
+    int32_t tiles_x;        // ceil(wn1 / 64)
+    double lam1, lam2;      // (1 - gamma) - kappa_c, (1 + gamma) - kappa_c
+    double mlo1, mlo2;      // map lower corner
+    double ms1, ms2;        // n_k / (hi_k - lo_k)
+    int32_t mn1, mn2;       // map size
+    int32_t window;         // LDS window side, 0 = all bins go to global atomics
+    uint32_t *partial;      // kPartials maps of mn1*mn2 bins, pstride words apart
+    int64_t pstride;        // words between partial maps (multiple of 64)
+    unsigned long long *lost;
+    double *ray_y;          // optional per-ray dump (window-relative index)
+    int32_t *ray_pix;
+};
+
+// Launch the direct-sum kernel for the given (K rays per lane, T-lens float32 runs, LT-lens tiles).
+hipError_t launch_direct(const DirectArgs &a, int K, int T, int LT, int64_t n_tiles, hipStream_t s);
+// Zero the partial maps (fill kernel; graph-capture safe).
+hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s);
+// counts[b] += sum_s partial[s * pstride + b] for b < bins.
+hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride, uint32_t *counts,
+                         hipStream_t s);
+
+}  // namespace rs

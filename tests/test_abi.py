@@ -1,0 +1,159 @@
+"""Host-side checks of the C ABI (no GPU needed): exports, validation and error paths.
+
+Every call here fails validation (or is the fault-injection path) before the
+library makes any HIP call, so fake device addresses are safe.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rs.h")
+
+
+def _lib():
+    import paper_0905_2453_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("librs.so not built")
+    return P, P.lib()
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_functions_exported():
+    P, L = _lib()
+    names = _declared_functions()
+    assert "rs_shoot" in names and "rs_workspace_bytes" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in rs.h but not exported"
+    from paper_0905_2453_amd import _abi
+    assert sorted(e[0] for e in _abi.EXPORTS) == names
+
+
+def test_struct_layout_matches_header_sizes():
+    from paper_0905_2453_amd import _abi
+    assert ctypes.sizeof(_abi.Macro) == 16
+    assert ctypes.sizeof(_abi.RayGrid) == 16 + 16 + 16 + 16 + 16
+    assert ctypes.sizeof(_abi.Map) == 16 + 16 + 8
+    assert ctypes.sizeof(_abi.Opts) == 4 * 4 + 8 + 8 + 8
+
+
+def _job(**kw):
+    from paper_0905_2453_amd import _abi
+    j = _abi.Job()
+    j.lenses = ctypes.c_void_p(0x1000)
+    j.n_lens = 10
+    j.macro.kappa_c, j.macro.gamma = 0.0, 0.1
+    for k in range(2):
+        j.grid.lo[k], j.grid.hi[k], j.grid.n[k] = -1.0, 1.0, 64
+        j.grid.win_lo[k], j.grid.win_n[k] = 0, 64
+        j.map.lo[k], j.map.hi[k], j.map.n[k] = -1.0, 1.0, 16
+    j.counts = ctypes.c_void_p(0x2000)
+    j.n_lost = ctypes.c_void_p(0x3000)
+    for key, v in kw.items():
+        obj, attr = j, key
+        if "." in key:
+            a, attr = key.split(".")
+            obj = getattr(j, a)
+        if isinstance(v, tuple):
+            getattr(obj, attr)[v[0]] = v[1]
+        else:
+            setattr(obj, attr, v)
+    return j
+
+
+def _shoot(L, job, ws_bytes=1 << 20, opts=None, ws=0x4000):
+    return L.rs_shoot(ctypes.byref(job), ctypes.c_void_p(ws), ws_bytes, None,
+                      ctypes.byref(opts) if opts is not None else None)
+
+
+def test_workspace_query():
+    P, L = _lib()
+    j = _job()
+    n = L.rs_workspace_bytes(ctypes.byref(j), None)
+    assert n >= 8 * 16 * 16 * 4
+    assert L.rs_workspace_bytes(ctypes.byref(_job(n_lens=-1)), None) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_lens=-1), -1),
+    (dict(lenses=None), -1),
+    (dict(counts=None), -1),
+    (dict(n_lost=None), -1),
+    (dict(**{"grid.n": (0, 0)}), -1),
+    (dict(**{"grid.hi": (1, -1.0)}), -1),
+    (dict(**{"grid.lo": (0, float("nan"))}), -1),
+    (dict(**{"grid.win_lo": (0, 10)}), -1),
+    (dict(**{"grid.win_n": (1, 65)}), -1),
+    (dict(**{"grid.win_lo": (1, -1)}), -1),
+    (dict(**{"map.n": (0, -3)}), -1),
+    (dict(**{"map.hi": (0, -2.0)}), -1),
+    (dict(**{"macro.gamma": float("inf")}), -1),
+    (dict(**{"grid.lo": (0, -1e13)}), -1),
+])
+def test_invalid_arguments_rejected(kw, code):
+    P, L = _lib()
+    st = _shoot(L, _job(**kw))
+    assert st == code, L.rs_last_error()
+    assert L.rs_status_str(st) == b"RS_EINVAL"
+    assert len(L.rs_last_error()) > 0
+
+
+def test_too_many_rays_is_range_error():
+    P, L = _lib()
+    j = _job()
+    for k in range(2):
+        j.grid.n[k] = 1 << 16
+        j.grid.win_n[k] = 1 << 16
+    assert _shoot(L, j) == -2
+
+
+def test_map_too_large_is_range_error():
+    P, L = _lib()
+    j = _job()
+    j.map.n[0] = 1 << 16
+    j.map.n[1] = 1 << 15
+    assert _shoot(L, j) == -2
+
+
+def test_small_workspace_and_null_workspace():
+    P, L = _lib()
+    j = _job()
+    need = L.rs_workspace_bytes(ctypes.byref(j), None)
+    assert _shoot(L, j, ws_bytes=need - 1) == -4
+    assert _shoot(L, j, ws=0) == -1
+
+
+def test_bad_opts_rejected():
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    for field, val in [("rays_per_lane", 5), ("lens_tile", 100), ("fp32_run", 7), ("map_window", 48)]:
+        o = _abi.Opts()
+        setattr(o, field, val)
+        assert _shoot(L, _job(), opts=o) == -1
+    o = _abi.Opts()
+    o.ray_y = 0x5000  # without ray_pix
+    assert _shoot(L, _job(), opts=o) == -1
+
+
+def test_fault_injection_reports_device_error_without_launch():
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    st = _shoot(L, _job(), opts=o)
+    assert st == -3 and b"injected" in L.rs_last_error()
+    with pytest.raises(P.RayShootError) as ei:
+        P._check(st)
+    assert ei.value.status == -3
+
+
+def test_version_string():
+    P, L = _lib()
+    assert b"gfx950" in L.rs_version()

@@ -1,0 +1,255 @@
+"""GPU parity of the direct inverse ray-shooting path (rs_shoot) against the FP64 oracle.
+
+Tolerances (the plain path): at most 1e-5 of the rays may land in a different
+pixel than the FP64 oracle puts them in (pixel or lost outcome compared ray by
+ray).  Results that do not depend on float32 rounding are compared exactly:
+integer counts against the kernel's own per-ray pixels, conservation,
+determinism, tiling invariance, window streaming, and N_* = 0 exact lattice
+counts.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SWITCH_TOL = 1e-5
+U32 = 2.0 ** -24
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _P():
+    import paper_0905_2453_amd as P
+    P.lib()  # raises if the HIP library is missing: no fallback
+    return P
+
+
+def run(w, opts=None, window=None, dump=False, lenses=None):
+    """Shoot a workload on cuda:0; returns (counts np.uint32, lost int, ray_y, ray_pix)."""
+    torch = _torch()
+    P = _P()
+    o = P.Opts() if opts is None else opts
+    dev = torch.device("cuda:0")
+    if lenses is None:
+        lenses = torch.from_numpy(np.ascontiguousarray(w.lenses)).to(dev)
+    if window is None:
+        window = ((0, 0), (w.grid_n[0], w.grid_n[1]))
+    nr = int(window[1][0]) * int(window[1][1])
+    ry = rp = None
+    if dump:
+        ry = torch.full((max(nr, 1), 2), float("nan"), dtype=torch.float64, device=dev)
+        rp = torch.full((max(nr, 1),), -7, dtype=torch.int32, device=dev)
+        o.ray_y = ry.data_ptr()
+        o.ray_pix = rp.data_ptr()
+    counts, lost = P.shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
+                           w.map_n, window=window, opts=o)
+    torch.cuda.synchronize()
+    out = (counts.cpu().numpy().view(np.uint32), int(lost.item()))
+    if dump:
+        return out + (ry.cpu().numpy()[:nr], rp.cpu().numpy()[:nr])
+    return out + (None, None)
+
+
+def switch_fraction(pix_a, pix_b):
+    """Rays whose (pixel or lost) outcome differs / rays in the map in either run."""
+    diff = np.sum(pix_a != pix_b)
+    inmap = np.sum((pix_a >= 0) | (pix_b >= 0))
+    return diff / max(1, inmap), int(diff)
+
+
+def test_small_workload_full_parity():
+    w = synth.workload_small()
+    counts, lost, ry, rp = run(w, dump=True)
+    n = w.n_rays
+    # conservation and binning are exact
+    assert int(counts.sum()) + lost == n
+    assert np.array_equal(counts.ravel().astype(np.int64),
+                          np.bincount(rp[rp >= 0], minlength=counts.size))
+    assert lost == int(np.sum(rp == -1))
+    # every ray against the oracle
+    y_o, p_o = oracle.trace_parallel(w, np.arange(n))
+    frac, nd = switch_fraction(rp.astype(np.int64), p_o)
+    print(f"small workload: {nd} of {n} rays switch pixel (fraction {frac:.2e})")
+    assert frac <= SWITCH_TOL
+    # map agreement follows: per-pixel |diff| summed is at most 2 x switched rays
+    co, lo_ = oracle.shoot_parallel(w)
+    assert np.abs(counts.astype(np.int64) - co.astype(np.int64)).sum() <= 2 * nd
+    # per-ray source positions within the float32 forward-error bound
+    ok = np.isfinite(y_o).all(1) & np.isfinite(ry).all(1)
+    L = w.lenses.astype(np.float64)
+    xs1 = oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0]).astype(np.float64)
+    idx = np.nonzero(ok)[0][::97]
+    x = np.stack([xs1[idx % w.grid_n[0]], xs1[idx // w.grid_n[0]]], 1)
+    s = np.zeros(len(idx))
+    for rec in L:
+        s += rec[2] / np.hypot(x[:, 0] - rec[0], x[:, 1] - rec[1])
+    bound = (8 + 16) * U32 * s + 1e-12
+    err = np.abs(ry[idx] - y_o[idx]).max(1)
+    assert np.all(err <= bound), (err / bound).max()
+
+
+def test_deterministic_and_tiling_invariant():
+    w = synth.workload_small(seed=9)
+    P = _P()
+    ref = run(w, dump=True)
+    again = run(w, dump=True)
+    assert np.array_equal(ref[0], again[0]) and ref[1] == again[1]
+    assert np.array_equal(ref[2], again[2])
+    # rays per lane, lens tile and map window change speed only, never values
+    for K, LT, W in [(4, 256, 16), (16, 512, 64), (8, 512, -1), (4, 512, 32)]:
+        o = P.Opts()
+        o.rays_per_lane, o.lens_tile, o.map_window = K, LT, W
+        got = run(w, opts=o, dump=True)
+        assert np.array_equal(got[0], ref[0]), (K, LT, W)
+        assert got[1] == ref[1]
+        assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3])
+
+
+@pytest.mark.parametrize("T", [8, 32])
+def test_fp32_run_length_variants_within_tolerance(T):
+    P = _P()
+    w = synth.workload_small(seed=3)
+    o = P.Opts()
+    o.fp32_run = T
+    counts, lost, ry, rp = run(w, opts=o, dump=True)
+    _, p_o = oracle.trace_parallel(w, np.arange(w.n_rays))
+    frac, nd = switch_fraction(rp.astype(np.int64), p_o)
+    assert frac <= SWITCH_TOL, (T, nd)
+    assert int(counts.sum()) + lost == w.n_rays
+
+
+def test_dump_does_not_change_map():
+    w = synth.workload_small(seed=4)
+    a = run(w)
+    b = run(w, dump=True)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+def test_window_streaming_adds_up():
+    torch = _torch()
+    P = _P()
+    w = synth.workload_small(seed=5)
+    full = run(w)
+    dev = torch.device("cuda:0")
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    # ragged, uneven windows in both axes
+    for (a, b) in [((0, 0), (1000, 137)), ((0, 137), (301, 863)), ((301, 137), (699, 500)),
+                   ((301, 637), (699, 363))]:
+        P.shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                counts=counts, lost=lost, window=(a, b))
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), full[0])
+    assert int(lost.item()) == full[1]
+
+
+@pytest.mark.parametrize("n_lens", [1, 255, 257, 1000])
+def test_ragged_lens_counts_and_grid(n_lens):
+    lenses, r = synth.lens_field(30 + n_lens, n_lens, kappa_star=0.3)
+    lo, hi, n = synth.shooting_region((4.0, 3.0), 0.3, 0.1, (203, 77), r)
+    w = synth.Workload("ragged", lenses, 0.05, 0.1, lo, hi, n, (-4.0, -3.0), (4.0, 3.0), (37, 23))
+    counts, lost, ry, rp = run(w, dump=True)
+    assert int(counts.sum()) + lost == w.n_rays
+    assert np.array_equal(counts.ravel().astype(np.int64), np.bincount(rp[rp >= 0], minlength=counts.size))
+    _, p_o = oracle.trace(w, np.arange(w.n_rays))
+    frac, nd = switch_fraction(rp.astype(np.int64), p_o)
+    assert nd <= max(1, int(SWITCH_TOL * w.n_rays)), nd
+
+
+def test_empty_window_and_no_lenses():
+    torch = _torch()
+    w = synth.Workload("sheet", np.zeros((0, 4), np.float32), 0.25, 0.125, (-8.0, -6.0), (8.0, 6.0),
+                       (256, 192), (-3.0, -2.5), (3.0, 2.5), (24, 20))
+    counts, lost, _, _ = run(w, window=((10, 10), (0, 50)))
+    assert counts.sum() == 0 and lost == 0
+    counts, lost, _, _ = run(w)
+    assert int(counts.sum()) + lost == w.n_rays
+
+
+def _exact_axis_counts(lo, hi, n, lam, mlo, mhi, mn):
+    from fractions import Fraction
+    from oracle import exact
+    out = np.zeros(mn, dtype=np.int64)
+    for i in range(n):
+        X = Fraction(exact.round_to_float32(exact.exact_coord(lo, hi, n, i)))
+        p = math.floor((Fraction(lam) * X - Fraction(mlo)) * mn / (Fraction(mhi) - Fraction(mlo)))
+        if 0 <= p < mn:
+            out[p] += 1
+    return out
+
+
+@pytest.mark.parametrize("kappa_c,gamma", [(0.25, 0.125), (1.25, 0.0), (0.5, -0.25)])
+def test_smooth_sheet_exact_counts_on_gpu(kappa_c, gamma):
+    w = synth.Workload("sheet", np.zeros((0, 4), np.float32), kappa_c, gamma, (-8.0, -6.0), (8.0, 6.0),
+                       (256, 192), (-3.0, -2.5), (3.0, 2.5), (24, 20))
+    counts, lost, _, _ = run(w)
+    c1 = _exact_axis_counts(-8.0, 8.0, 256, 1 - kappa_c - gamma, -3.0, 3.0, 24)
+    c2 = _exact_axis_counts(-6.0, 6.0, 192, 1 - kappa_c + gamma, -2.5, 2.5, 20)
+    assert np.array_equal(counts.astype(np.int64), np.outer(c2, c1))
+
+
+def test_single_lens_disc_count_identity_on_gpu():
+    L = np.array([[0.0, 0.0, 1.0, 0.0]], dtype=np.float32)
+    w = synth.Workload("one", L, 0.0, 0.0, (-4.0, -4.0), (4.0, 4.0), (600, 600), (-4.0, -4.0), (4.0, 4.0),
+                       (8, 8))
+    _, _, ry, _ = run(w, dump=True)
+    xs = oracle.axis(-4.0, 4.0, 600).astype(np.float64)
+    X1, X2 = np.meshgrid(xs, xs)
+    rx = np.hypot(X1, X2).ravel()
+    r_y = np.hypot(ry[:, 0], ry[:, 1])
+    for u in (0.1, 0.5, 1.0, 2.0, 3.0):
+        rp_ = (math.sqrt(u * u + 4) + u) / 2
+        rm_ = (math.sqrt(u * u + 4) - u) / 2
+        amb = (np.abs(rx - rp_) < 1e-5) | (np.abs(rx - rm_) < 1e-5) | (np.abs(r_y - u) < 1e-5)
+        assert np.sum((r_y < u) & ~amb) == np.sum((rx > rm_) & (rx < rp_) & ~amb)
+
+
+def test_ray_on_lens_is_lost_on_gpu():
+    xs = oracle.axis(-1.0, 1.0, 8)
+    L = np.array([[xs[3], xs[5], 1.0, 0]], dtype=np.float32)
+    w = synth.Workload("hit", L, 0.0, 0.0, (-1.0, -1.0), (1.0, 1.0), (8, 8), (-4.0, -4.0), (4.0, 4.0), (4, 4))
+    counts, lost, ry, rp = run(w, dump=True)
+    assert rp[5 * 8 + 3] == -1
+    _, p_o = oracle.trace(w, np.arange(64))
+    assert np.array_equal(rp.astype(np.int64), p_o)
+
+
+def test_paper_scale_sampled_parity():
+    # 1e5 power-law lenses, kappa_*=0.45, gamma=0.45, 4096^2 rays, 1024^2 map: the full
+    # workload in the launch configuration the benchmark times; 2^16 sampled rays checked
+    # one by one against the FP64 oracle.
+    w = synth.workload_paper()
+    counts, lost, ry, rp = run(w, dump=True)
+    assert int(counts.sum()) + lost == w.n_rays
+    assert np.array_equal(counts.ravel().astype(np.int64), np.bincount(rp[rp >= 0], minlength=counts.size))
+    idx = synth.sample_indices(12, w.n_rays, 1 << 16)
+    y_o, p_o = oracle.trace_parallel(w, idx, threads=16)
+    frac, nd = switch_fraction(rp[idx].astype(np.int64), p_o)
+    ok = np.isfinite(y_o).all(1) & (p_o >= 0)
+    dpix = (w.map_hi[0] - w.map_lo[0]) / w.map_n[0]
+    dy = ry[idx][ok] - y_o[ok]
+    # For source positions spread uniformly over a pixel, a ray with error (d1, d2) changes
+    # pixel with probability (|d1| + |d2|) / pixel: the mean is the expected switch fraction,
+    # a far sharper estimate than counting switches in a sample.
+    est = np.mean(np.abs(dy).sum(1)) / dpix
+    # No systematic error proportional to the deflection (a biased reciprocal would show here).
+    lam1 = (1 - w.gamma) - w.kappa_c
+    xs1 = oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0]).astype(np.float64)
+    a1 = lam1 * xs1[idx[ok] % w.grid_n[0]] - y_o[ok, 0]
+    slope = float(np.dot(dy[:, 0], a1) / np.dot(a1, a1))
+    print(f"paper-scale sample: {nd} of {len(idx)} rays switch; estimated switch fraction {est:.2e}; "
+          f"error/deflection slope {slope:.2e}")
+    assert est <= SWITCH_TOL
+    assert abs(slope) < 1.5e-9
+    assert nd <= 4

@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="paper", choices=["paper", "small"])
-    ap.add_argument("--rays-per-lane", type=int, default=0)
+    ap.add_argument("--block", default="", help="rays per lane as COLSxROWS, e.g. 2x4 (default: library's)")
     ap.add_argument("--lens-tile", type=int, default=0)
     ap.add_argument("--fp32-run", type=int, default=0)
     ap.add_argument("--map-window", type=int, default=0)
@@ -92,7 +92,9 @@ def main():
     counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
     lost = torch.zeros(1, dtype=torch.int64, device=dev)
     opts = P.Opts()
-    opts.rays_per_lane, opts.lens_tile = args.rays_per_lane, args.lens_tile
+    if args.block:
+        opts.block_cols, opts.block_rows = (int(v) for v in args.block.lower().split("x"))
+    opts.lens_tile = args.lens_tile
     opts.fp32_run, opts.map_window = args.fp32_run, args.map_window
     job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                      counts, lost)

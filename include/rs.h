@@ -115,7 +115,8 @@ typedef struct {
  * before each FP64 addition); the other fields change speed, not values.
  */
 typedef struct {
-    int32_t rays_per_lane;   /* rays held in registers per lane: 4, 8 or 16 (default 4)        */
+    int32_t block_cols;      /* rays per lane: block_cols grid columns x block_rows grid rows;  */
+    int32_t block_rows;      /* 1x4, 2x2, 2x4, 4x2, 4x4 or 2x8 (0, 0 = default)               */
     int32_t lens_tile;       /* lenses staged in LDS per tile: 256 or 512 (default 256)        */
     int32_t fp32_run;        /* lenses per float32 run: 8, 16 or 32 (default 16)               */
     int32_t map_window;      /* side of the LDS-privatised map window: 16, 32 or 64; -1 = off */

@@ -45,9 +45,9 @@ class Job(ctypes.Structure):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("rays_per_lane", ctypes.c_int32), ("lens_tile", ctypes.c_int32), ("fp32_run", ctypes.c_int32),
-                ("map_window", ctypes.c_int32), ("ray_y", ctypes.c_void_p), ("ray_pix", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32)]
+    _fields_ = [("block_cols", ctypes.c_int32), ("block_rows", ctypes.c_int32), ("lens_tile", ctypes.c_int32),
+                ("fp32_run", ctypes.c_int32), ("map_window", ctypes.c_int32), ("ray_y", ctypes.c_void_p),
+                ("ray_pix", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
 # (name, restype, argtypes) of every exported function

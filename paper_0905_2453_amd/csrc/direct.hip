@@ -4,13 +4,15 @@
 // Method: Thompson, Fluke, Barnes & Barsdell (2009), section 1 eqs. 1, 2, 4; section 2 eq. 5;
 // section 3.2 eq. 6; the 10-flop interaction of appendix A.
 //
-// Work decomposition.  A workgroup of 4 wave64s owns a tile of 64 grid columns x (4 K) grid
-// rows: lane l of wave w holds the K rays (column c0 + l, rows r0 + w K + k), k < K.  The K
-// rays of a lane share x1, so x1 - x1_i and its square are computed once per lens and each
-// ray-lens interaction costs a subtract, an FMA (r^2), a reciprocal, a multiply (m / r^2) and
-// two FMAs (alpha).  Lenses stream through LDS in tiles of LT records (double buffered); every
-// lane reads the same record, so each LDS read is a broadcast.  Partial sums run in float32
-// over T consecutive lenses, then are added to a per-ray FP64 accumulator.
+// Work decomposition.  A workgroup of 4 wave64s owns a tile of (64 K1) grid columns x (4 K2)
+// grid rows: lane l of wave w holds the K1 x K2 block of rays at columns c0 + K1 l + a (a < K1)
+// and rows r0 + K2 w + b (b < K2).  Per lens, x1 - x1_i and its square are computed once per
+// column and x2 - x2_i once per row.  With several columns per lane the mass is folded into
+// those shared differences (m dx, m dy), so each ray-lens interaction costs one FMA (r^2), a
+// reciprocal and two FMAs (alpha += (1/r^2) (m dx)), plus (3 K1 + 2 K2) / (K1 K2) shared
+// operations; with one column the interaction keeps the multiply d = m / r^2.  Lenses stream through LDS in tiles of LT records (double buffered); every lane
+// reads the same record, so each LDS read is a broadcast.  Partial sums run in float32 over
+// T consecutive lenses, then are added to a per-ray FP64 accumulator.
 #include "rs_internal.h"
 
 namespace rs {
@@ -45,11 +47,13 @@ __device__ __forceinline__ float4 pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
-template <int K, int T, int LT, bool DUMP>
+template <int K1, int K2, int T, int LT, bool DUMP>
 __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 {
     static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
     constexpr int PER = LT / kThreads;
+    constexpr int R = K1 * K2;
+    constexpr bool FOLD = K1 >= 2;  // fold m into shared differences when a lane has several columns
     __shared__ float4 s_lens[2][LT];
     __shared__ uint32_t s_win[kMaxWindow * kMaxWindow];
     __shared__ int s_cand[2][2 * kWaves];
@@ -60,20 +64,22 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     const int wave = tid >> 6;
     const int tx = (int)(blockIdx.x % (uint32_t)a.tiles_x);
     const int ty = (int)(blockIdx.x / (uint32_t)a.tiles_x);
-    const int64_t c1 = (int64_t)tx * 64 + lane;
-    const int64_t r0 = (int64_t)ty * (kWaves * K) + (int64_t)wave * K;
+    const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
+    const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
 
-    const float x1 = ray_coord(a.glo1, a.gt1, a.wlo1 + c1);
-    float x2[K];
+    float x1[K1], x2[K2];
 #pragma unroll
-    for (int k = 0; k < K; ++k) x2[k] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + k);
+    for (int i = 0; i < K1; ++i) x1[i] = ray_coord(a.glo1, a.gt1, a.wlo1 + c0 + i);
+#pragma unroll
+    for (int b = 0; b < K2; ++b) x2[b] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + b);
 
     for (int b = tid; b < kMaxWindow * kMaxWindow; b += kThreads) s_win[b] = 0u;
     if (tid == 0) s_lost = 0u;
 
-    double A1[K], A2[K];
+    // ray (i, b) of the lane is slot i * K2 + b
+    double A1[R], A2[R];
 #pragma unroll
-    for (int k = 0; k < K; ++k) { A1[k] = 0.0; A2[k] = 0.0; }
+    for (int k = 0; k < R; ++k) { A1[k] = 0.0; A2[k] = 0.0; }
 
     const int64_t n_tiles = (a.n_lens + LT - 1) / LT;
     float4 reg[PER];
@@ -99,28 +105,68 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
         }
         const float4 *L = s_lens[buf];
         for (int r = 0; r < LT; r += T) {
-            float s1[K], s2[K];
+            float s1[R], s2[R];
 #pragma unroll
             for (int j = 0; j < T; ++j) {
                 const float4 l = L[r + j];
-                const float dx = x1 - l.x;
-                const float dx2 = dx * dx;
+                if constexpr (FOLD) {
+                    // shared per column: x1 - x1_i, its square and m (x1 - x1_i);
+                    // per row: x2 - x2_i and m (x2 - x2_i)
+                    float dx[K1], dx2[K1], mdx[K1], dy[K2], mdy[K2];
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float dy = x2[k] - l.y;
-                    const float r2 = fmaf(dy, dy, dx2);
-                    const float d = l.z * __builtin_amdgcn_rcpf(r2);
-                    if (j == 0) {
-                        s1[k] = d * dx;
-                        s2[k] = d * dy;
-                    } else {
-                        s1[k] = fmaf(d, dx, s1[k]);
-                        s2[k] = fmaf(d, dy, s2[k]);
+                    for (int i = 0; i < K1; ++i) {
+                        dx[i] = x1[i] - l.x;
+                        dx2[i] = dx[i] * dx[i];
+                        mdx[i] = l.z * dx[i];
+                    }
+#pragma unroll
+                    for (int b = 0; b < K2; ++b) {
+                        dy[b] = x2[b] - l.y;
+                        mdy[b] = l.z * dy[b];
+                    }
+#pragma unroll
+                    for (int i = 0; i < K1; ++i) {
+#pragma unroll
+                        for (int b = 0; b < K2; ++b) {
+                            const int k = i * K2 + b;
+                            const float q = __builtin_amdgcn_rcpf(fmaf(dy[b], dy[b], dx2[i]));
+                            if (j == 0) {
+                                s1[k] = q * mdx[i];
+                                s2[k] = q * mdy[b];
+                            } else {
+                                s1[k] = fmaf(q, mdx[i], s1[k]);
+                                s2[k] = fmaf(q, mdy[b], s2[k]);
+                            }
+                        }
+                    }
+                } else {
+                    // one column per lane: d = m / r^2 per ray, then alpha += d (dx, dy)
+                    float dx[K1], dx2[K1];
+#pragma unroll
+                    for (int i = 0; i < K1; ++i) {
+                        dx[i] = x1[i] - l.x;
+                        dx2[i] = dx[i] * dx[i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < K1; ++i) {
+#pragma unroll
+                        for (int b = 0; b < K2; ++b) {
+                            const int k = i * K2 + b;
+                            const float dy = x2[b] - l.y;
+                            const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx2[i]));
+                            if (j == 0) {
+                                s1[k] = d * dx[i];
+                                s2[k] = d * dy;
+                            } else {
+                                s1[k] = fmaf(d, dx[i], s1[k]);
+                                s2[k] = fmaf(d, dy, s2[k]);
+                            }
+                        }
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < R; ++k) {
                 A1[k] += (double)s1[k];
                 A2[k] += (double)s2[k];
             }
@@ -137,29 +183,32 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     // lenses this bias would dominate the float32 error of large deflections, so the FP64 sum
     // is rescaled by the inverse factor (two FP64 multiplies per ray, no per-lens cost).
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < R; ++k) {
         A1[k] *= kRcpBiasComp;
         A2[k] *= kRcpBiasComp;
     }
 
     // Lens equation (eq. 6) and source pixel, FP64.
-    const bool col_ok = c1 < a.wn1;
-    int key[K], q1[K], q2[K];
+    int key[R], q1[R], q2[R];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const bool ok = col_ok && (r0 + k < a.wn2);
-        const double y1 = a.lam1 * (double)x1 - A1[k];
-        const double y2 = a.lam2 * (double)x2[k] - A2[k];
-        int p1 = 0, p2 = 0;
-        const int kv = pixel_of(y1, y2, a, p1, p2);
-        key[k] = ok ? kv : -2;
-        q1[k] = p1;
-        q2[k] = p2;
-        if (DUMP && ok) {
-            const int64_t ri = (r0 + k) * a.wn1 + c1;
-            a.ray_y[2 * ri] = y1;
-            a.ray_y[2 * ri + 1] = y2;
-            a.ray_pix[ri] = kv;
+    for (int i = 0; i < K1; ++i) {
+#pragma unroll
+        for (int b = 0; b < K2; ++b) {
+            const int k = i * K2 + b;
+            const bool ok = (c0 + i < a.wn1) && (r0 + b < a.wn2);
+            const double y1 = a.lam1 * (double)x1[i] - A1[k];
+            const double y2 = a.lam2 * (double)x2[b] - A2[k];
+            int p1 = 0, p2 = 0;
+            const int kv = pixel_of(y1, y2, a, p1, p2);
+            key[k] = ok ? kv : -2;
+            q1[k] = p1;
+            q2[k] = p2;
+            if (DUMP && ok) {
+                const int64_t ri = (r0 + b) * a.wn1 + c0 + i;
+                a.ray_y[2 * ri] = y1;
+                a.ray_y[2 * ri + 1] = y2;
+                a.ray_pix[ri] = kv;
+            }
         }
     }
 
@@ -168,7 +217,7 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     const int W = a.window;
     int o1 = 0, o2 = 0;
     if (W > 0) {
-        constexpr int ka = K / 4, kb = (3 * K) / 4;
+        constexpr int ka = (K1 / 2) * K2 + K2 / 4, kb = (K1 / 2) * K2 + (3 * K2) / 4;
         if (lane == 16) {
             s_cand[0][2 * wave] = key[ka] >= 0 ? q1[ka] : INT_MIN;
             s_cand[1][2 * wave] = key[ka] >= 0 ? q2[ka] : INT_MIN;
@@ -204,7 +253,7 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     uint32_t *part = a.partial + (size_t)(blockIdx.x & (kPartials - 1)) * (size_t)a.pstride;
     uint32_t lost_cnt = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < R; ++k) {
         const int kv = key[k];
         const int prev = __shfl_up(kv, 1);
         const bool head = (lane == 0) || (kv != prev);
@@ -272,42 +321,49 @@ __global__ void __launch_bounds__(256) k_reduce(const uint32_t *partial, int64_t
     }
 }
 
-template <int K, int T, int LT>
+template <int K1, int K2, int T, int LT>
 hipError_t launch_kt(const DirectArgs &a, int64_t n_tiles, hipStream_t s)
 {
     if (a.ray_y)
-        hipLaunchKernelGGL((k_direct<K, T, LT, true>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_direct<K1, K2, T, LT, true>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_direct<K, T, LT, false>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_direct<K1, K2, T, LT, false>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-template <int K>
+template <int K1, int K2>
 hipError_t launch_k(const DirectArgs &a, int T, int LT, int64_t n_tiles, hipStream_t s)
 {
     if (LT == 256) {
-        if (T == 8) return launch_kt<K, 8, 256>(a, n_tiles, s);
-        if (T == 16) return launch_kt<K, 16, 256>(a, n_tiles, s);
-        if (T == 32) return launch_kt<K, 32, 256>(a, n_tiles, s);
+        if (T == 8) return launch_kt<K1, K2, 8, 256>(a, n_tiles, s);
+        if (T == 16) return launch_kt<K1, K2, 16, 256>(a, n_tiles, s);
+        if (T == 32) return launch_kt<K1, K2, 32, 256>(a, n_tiles, s);
     } else if (LT == 512) {
-        if (T == 8) return launch_kt<K, 8, 512>(a, n_tiles, s);
-        if (T == 16) return launch_kt<K, 16, 512>(a, n_tiles, s);
-        if (T == 32) return launch_kt<K, 32, 512>(a, n_tiles, s);
+        if (T == 8) return launch_kt<K1, K2, 8, 512>(a, n_tiles, s);
+        if (T == 16) return launch_kt<K1, K2, 16, 512>(a, n_tiles, s);
+        if (T == 32) return launch_kt<K1, K2, 32, 512>(a, n_tiles, s);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_direct(const DirectArgs &a, int K, int T, int LT, int64_t n_tiles, hipStream_t s)
+bool ray_block_supported(int K1, int K2)
+{
+    return (K1 == 1 && K2 == 4) || (K1 == 2 && K2 == 2) || (K1 == 2 && K2 == 4) || (K1 == 4 && K2 == 2) ||
+           (K1 == 4 && K2 == 4) || (K1 == 2 && K2 == 8);
+}
+
+hipError_t launch_direct(const DirectArgs &a, int K1, int K2, int T, int LT, int64_t n_tiles, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    switch (K) {
-    case 4: return launch_k<4>(a, T, LT, n_tiles, s);
-    case 8: return launch_k<8>(a, T, LT, n_tiles, s);
-    case 16: return launch_k<16>(a, T, LT, n_tiles, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (K1 == 1 && K2 == 4) return launch_k<1, 4>(a, T, LT, n_tiles, s);
+    if (K1 == 2 && K2 == 2) return launch_k<2, 2>(a, T, LT, n_tiles, s);
+    if (K1 == 2 && K2 == 4) return launch_k<2, 4>(a, T, LT, n_tiles, s);
+    if (K1 == 4 && K2 == 2) return launch_k<4, 2>(a, T, LT, n_tiles, s);
+    if (K1 == 4 && K2 == 4) return launch_k<4, 4>(a, T, LT, n_tiles, s);
+    if (K1 == 2 && K2 == 8) return launch_k<2, 8>(a, T, LT, n_tiles, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s)

@@ -30,16 +30,18 @@ constexpr double kMaxCoord = 1.0e12;  // far below the position of the zero-mass
 
 // Resolved tuning of one direct-sum launch.
 struct Tune {
-    int K = 4, T = 16, LT = 256, W = 64;
+    int K1 = 1, K2 = 4, T = 16, LT = 256, W = 64;
 };
 
 int resolve_opts(const rs_opts *o, Tune &t)
 {
     if (!o) return RS_OK;
-    if (o->rays_per_lane) {
-        if (o->rays_per_lane != 4 && o->rays_per_lane != 8 && o->rays_per_lane != 16)
-            return fail(RS_EINVAL, "rays_per_lane must be 4, 8 or 16 (got %d)", o->rays_per_lane);
-        t.K = o->rays_per_lane;
+    if (o->block_cols || o->block_rows) {
+        if (!rs::ray_block_supported(o->block_cols, o->block_rows))
+            return fail(RS_EINVAL, "unsupported ray block %d x %d (use 1x4, 2x2, 2x4, 4x2, 4x4 or 2x8)",
+                        o->block_cols, o->block_rows);
+        t.K1 = o->block_cols;
+        t.K2 = o->block_rows;
     }
     if (o->lens_tile) {
         if (o->lens_tile != 256 && o->lens_tile != 512)
@@ -172,8 +174,9 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
     a.ray_y = opts ? opts->ray_y : nullptr;
     a.ray_pix = opts ? opts->ray_pix : nullptr;
 
-    const int64_t tiles_x = (g.win_n[0] + 63) / 64;
-    const int64_t rows = (int64_t)rs::kWaves * t.K;
+    const int64_t cols = 64 * (int64_t)t.K1;
+    const int64_t tiles_x = (g.win_n[0] + cols - 1) / cols;
+    const int64_t rows = (int64_t)rs::kWaves * t.K2;
     const int64_t tiles_y = (g.win_n[1] + rows - 1) / rows;
     if (tiles_x * tiles_y >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
     a.tiles_x = (int32_t)tiles_x;
@@ -181,7 +184,7 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = rs::launch_zero(part, rs::kPartials * pstride, s);
     if (e != hipSuccess) return dev_fail(e, "zero partial maps");
-    e = rs::launch_direct(a, t.K, t.T, t.LT, tiles_x * tiles_y, s);
+    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, tiles_x * tiles_y, s);
     if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");

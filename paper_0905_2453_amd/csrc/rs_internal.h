@@ -8,7 +8,7 @@
 
 namespace rs {
 
-// Rays of one workgroup tile: 64 grid columns (one per lane) x (WAVES * K) rows.
+// A workgroup tile is (64 K1) grid columns x (kWaves K2) grid rows; see ray_block_shape.
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxWindow = 64;          // LDS map window side (bins)
@@ -23,7 +23,7 @@ struct DirectArgs {
     double gt1, gt2;        // grid cell size (hi - lo) / n, computed on the host in FP64
     int64_t wlo1, wlo2;     // ray window origin (grid indices)
     int64_t wn1, wn2;       // ray window size
-    int32_t tiles_x;        // ceil(wn1 / 64)
+    int32_t tiles_x;        // ceil(wn1 / (64 K1))
     double lam1, lam2;      // (1 - gamma) - kappa_c, (1 + gamma) - kappa_c
     double mlo1, mlo2;      // map lower corner
     double ms1, ms2;        // n_k / (hi_k - lo_k)
@@ -36,8 +36,11 @@ struct DirectArgs {
     int32_t *ray_pix;
 };
 
-// Launch the direct-sum kernel for the given (K rays per lane, T-lens float32 runs, LT-lens tiles).
-hipError_t launch_direct(const DirectArgs &a, int K, int T, int LT, int64_t n_tiles, hipStream_t s);
+// Per-lane ray blocks (K1 columns x K2 rows) compiled into the library.
+bool ray_block_supported(int K1, int K2);
+// Launch the direct-sum kernel for a K1 x K2 ray block per lane, T-lens float32 runs and LT-lens
+// LDS tiles.
+hipError_t launch_direct(const DirectArgs &a, int K1, int K2, int T, int LT, int64_t n_tiles, hipStream_t s);
 // Zero the partial maps (fill kernel; graph-capture safe).
 hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s);
 // counts[b] += sum_s partial[s * pstride + b] for b < bins.

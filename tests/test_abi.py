@@ -41,7 +41,7 @@ def test_struct_layout_matches_header_sizes():
     assert ctypes.sizeof(_abi.Macro) == 16
     assert ctypes.sizeof(_abi.RayGrid) == 16 + 16 + 16 + 16 + 16
     assert ctypes.sizeof(_abi.Map) == 16 + 16 + 8
-    assert ctypes.sizeof(_abi.Opts) == 4 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_abi.Opts) == 5 * 4 + 4 + 8 + 8 + 8
 
 
 def _job(**kw):
@@ -133,10 +133,14 @@ def test_small_workspace_and_null_workspace():
 def test_bad_opts_rejected():
     P, L = _lib()
     from paper_0905_2453_amd import _abi
-    for field, val in [("rays_per_lane", 5), ("lens_tile", 100), ("fp32_run", 7), ("map_window", 48)]:
+    for field, val in [("block_cols", 3), ("block_rows", 5), ("lens_tile", 100), ("fp32_run", 7),
+                       ("map_window", 48)]:
         o = _abi.Opts()
         setattr(o, field, val)
         assert _shoot(L, _job(), opts=o) == -1
+    o = _abi.Opts()
+    o.block_cols, o.block_rows = 4, 8
+    assert _shoot(L, _job(), opts=o) == -1
     o = _abi.Opts()
     o.ray_y = 0x5000  # without ray_pix
     assert _shoot(L, _job(), opts=o) == -1

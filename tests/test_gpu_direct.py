@@ -106,11 +106,12 @@ def test_deterministic_and_tiling_invariant():
     assert np.array_equal(ref[0], again[0]) and ref[1] == again[1]
     assert np.array_equal(ref[2], again[2])
     # rays per lane, lens tile and map window change speed only, never values
-    for K, LT, W in [(4, 256, 16), (16, 512, 64), (8, 512, -1), (4, 512, 32)]:
+    for (K1, K2), LT, W in [((1, 4), 256, 16), ((4, 4), 512, 64), ((2, 4), 512, -1), ((2, 2), 512, 32),
+                            ((4, 2), 256, 64), ((2, 8), 256, 32)]:
         o = P.Opts()
-        o.rays_per_lane, o.lens_tile, o.map_window = K, LT, W
+        o.block_cols, o.block_rows, o.lens_tile, o.map_window = K1, K2, LT, W
         got = run(w, opts=o, dump=True)
-        assert np.array_equal(got[0], ref[0]), (K, LT, W)
+        assert np.array_equal(got[0], ref[0]), (K1, K2, LT, W)
         assert got[1] == ref[1]
         assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3])
 

@@ -42,7 +42,41 @@ def parse():
     ap.add_argument("--map-window", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int):
+    """Plain copies of a known size, so HBM byte counters can be scaled against them."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
+
+
+def measured_traffic(workload_name: str, opts) -> float | None:
+    """HBM bytes per k_direct launch from the committed rocprofv3 counter passes, or None when the
+    kernel source or the launch shape differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("k_direct")
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or rec["workload"] != workload_name:
+        return None
+    cols, rows = (opts.block_cols or 1), (opts.block_rows or 4)
+    if f"{cols}x{rows}" != rec["block"] or (opts.fp32_run or 16) != rec["fp32_run"] \
+            or (opts.lens_tile or 256) != rec["lens_tile"]:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def workload(name):
@@ -75,6 +109,9 @@ def cpu_baseline(w, target_cpu_s: float):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in the design notes but not implemented", file=sys.stderr)
@@ -150,7 +187,7 @@ def main():
         "gflops": value * FLOP_PER_INTERACTION / 1e9,
         "rays_per_s": w.n_rays * args.steps / wall,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(w.name, opts),
                      "kernel": "k_direct", "flop_per_interaction": FLOP_PER_INTERACTION,
                      "kernel_ms": kernel_s * 1e3,
                      "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},

@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paper", choices=["paper", "small"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "small", "batched"])
+    ap.add_argument("--autotune-cache", default="", help="batched workload: autotuner cache file")
     ap.add_argument("--block", default="", help="rays per lane as COLSxROWS, e.g. 2x4 (default: library's)")
     ap.add_argument("--lens-tile", type=int, default=0)
     ap.add_argument("--fp32-run", type=int, default=0)
@@ -107,6 +108,85 @@ def cpu_baseline(w, target_cpu_s: float):
                       f"FP64 single-threaded oracle on {threads} threads, {dt:.1f} s wall"}
 
 
+def bench_batched(args):
+    """64 maps in one persistent, graph-replayed launch vs 64 separate rs_shoot launches."""
+    import torch
+    import paper_0905_2453_amd as P
+    import synth
+    dev = torch.device("cuda:0")
+    wl = synth.batched_jobs()
+    dj = []
+    for w in wl:
+        lenses = torch.from_numpy(w.lenses).to(dev)
+        counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+        lost = torch.zeros(1, dtype=torch.int64, device=dev)
+        dj.append((P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
+                              w.map_n, counts, lost), lenses, counts, lost))
+    jobs = [d[0] for d in dj]
+    ws = torch.empty(P.batched_workspace_bytes(jobs), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        opts = P.autotune_batched(jobs, ws, cache_path=args.autotune_cache or None, stream=stream)
+    tune_s = time.perf_counter() - t0
+    inter = float(sum(w.n_rays * w.n_lens for w in wl))
+    rays = float(sum(w.n_rays for w in wl))
+
+    def zero():
+        for d in dj:
+            d[2].zero_()
+            d[3].zero_()
+
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            P.shoot_batched(jobs, ws, opts, stream=stream)
+        stream.synchronize()
+        zero()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            P.shoot_batched(jobs, ws, opts, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        batched_ms = e0.elapsed_time(e1) / args.steps
+        total = sum(int(d[2].sum().item()) + int(d[3].item()) for d in dj)
+        if total != int(rays) * args.steps:
+            print("bench.py: ray conservation failed in the batch", file=sys.stderr)
+            sys.exit(3)
+        # 64 separate plain launches of the same maps (default rs_shoot tuning)
+        wss = [torch.empty(P.workspace_bytes(d[0]), dtype=torch.uint8, device=dev) for d in dj]
+        for d, w in zip(dj, wss):
+            P.shoot_job(d[0], w, None, stream)
+        stream.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            for d, w in zip(dj, wss):
+                P.shoot_job(d[0], w, None, stream)
+        e1.record(stream)
+        stream.synchronize()
+        separate_ms = e0.elapsed_time(e1) / args.steps
+    value = inter * args.steps / wall
+    out = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-64maps", "n_maps": len(wl), "interactions": inter, "rays": rays,
+                   "parallelism": "1 GPU"},
+        "gflops": value * FLOP_PER_INTERACTION / 1e9,
+        "batched_ms": batched_ms, "separate_launches_ms": separate_ms, "speedup_vs_separate": separate_ms / batched_ms,
+        "autotuned": {"block": f"{opts.block_cols}x{opts.block_rows}", "map_window": opts.map_window,
+                      "lens_tile": opts.lens_tile, "tune_seconds": tune_s},
+        "roofline": {"bound": "alu", "achieved": FLOP_PER_INTERACTION * inter / (batched_ms * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": FLOP_PER_INTERACTION * inter / (batched_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                     "traffic": None, "kernel": "k_batched"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -122,6 +202,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = workload(args.workload)

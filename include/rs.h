@@ -108,6 +108,7 @@ typedef struct {
 
 /* Flags for rs_opts.flags */
 #define RS_FLAG_FAULT_INJECT 0x1u  /* fail with RS_EDEVICE after validation, before any HIP call */
+#define RS_FLAG_NO_GRAPH 0x2u      /* rs_shoot_batched: launch directly instead of replaying a graph */
 
 /*
  * Tuning and diagnostics for rs_shoot.  NULL, or a zero field, selects the
@@ -140,6 +141,44 @@ size_t rs_workspace_bytes(const rs_job *job, const rs_opts *opts);
  * arguments, RS_EDEVICE if a launch fails.  An empty window is a no-op.
  */
 int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
+
+/*
+ * Many maps in one persistent launch (many independent map generations, section 4; each map is
+ * eqs. 1, 2, 4, 5, 6 exactly as rs_shoot computes it, so its counts are bit-identical to a
+ * rs_shoot call with the same block shape and fp32_run).
+ *
+ * Workspace bytes for a batch: work counter, job table, tile prefix sums and one scratch map
+ * (for the autotuner).  Returns 0 for an invalid batch.
+ */
+size_t rs_batched_workspace_bytes(const rs_job *jobs, int32_t n_jobs);
+
+/*
+ * Shoot every job of the host array jobs[0 .. n_jobs) and add each job's counts to its own map.
+ * Ray tiles of all jobs form one queue taken by a persistent kernel, costliest jobs first.  On a
+ * non-NULL stream the two kernels (counter reset, persistent kernel) are captured once into a
+ * HIP graph per (workspace address, block shape, grid, batch size) and replayed on later calls;
+ * the job table is uploaded into the workspace before each launch, so later calls may change
+ * the jobs' parameters and buffers.  opts: block shape, lens_tile, fp32_run, map_window and
+ * RS_FLAG_NO_GRAPH; per-ray dumps are rejected (RS_EINVAL).  Calls sharing a workspace must be
+ * ordered on one stream.  Returns as rs_shoot, with the failing job's index in rs_last_error.
+ */
+int rs_shoot_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, void *stream,
+                     const rs_opts *opts);
+
+/*
+ * Pick the block shape and map window for a batch by timing candidates (1x4, 2x4, 4x4, 2x8 ray
+ * blocks x 32/64 windows) on the batch's costliest tiles, with counts sent to the workspace's
+ * scratch map (the jobs' maps are not touched).  *best supplies fp32_run and lens_tile and
+ * receives block_cols, block_rows, lens_tile and map_window.  If cache_path (nullable) holds
+ * an entry for this device and batch class (median lens count, ray count and map size, in
+ * powers of two) it is used without timing; otherwise the result is appended to the file.
+ * Synchronises the stream.
+ */
+int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, void *stream,
+                        const char *cache_path, rs_opts *best);
+
+/* Destroy the cached batch graphs and staged job tables (e.g. before freeing workspaces). */
+void rs_release_graphs(void);
 
 #ifdef __cplusplus
 }

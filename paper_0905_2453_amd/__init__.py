@@ -132,3 +132,46 @@ def shoot_workload(w, device="cuda", opts: Opts | None = None, window=None, lens
         lenses = torch.from_numpy(w.lenses).to(device)
     return shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                  window=window, opts=opts, stream=stream)
+
+
+# ---------------------------------------------------------------- batches
+
+def job_array(jobs):
+    """A contiguous host array of rs_job structs (keeps no reference to the tensors)."""
+    return (_abi.Job * len(jobs))(*jobs)
+
+
+def batched_workspace_bytes(jobs) -> int:
+    arr = job_array(jobs)
+    n = lib().rs_batched_workspace_bytes(arr, len(jobs))
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+def shoot_batched(jobs, workspace, opts: Opts | None = None, stream=None) -> None:
+    """rs_shoot_batched: every job's counts are added to its own map (one persistent launch)."""
+    _require_cuda(workspace, "workspace")
+    arr = job_array(jobs)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().rs_shoot_batched(arr, len(jobs), ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                                  _stream_handle(stream), ctypes.byref(opts) if opts else None))
+
+
+def autotune_batched(jobs, workspace, cache_path: str | None = None, opts: Opts | None = None,
+                     stream=None) -> Opts:
+    """rs_autotune_batched: the fastest block shape / window for this batch (synchronises)."""
+    _require_cuda(workspace, "workspace")
+    best = Opts()
+    if opts is not None:
+        ctypes.memmove(ctypes.byref(best), ctypes.byref(opts), ctypes.sizeof(Opts))
+    arr = job_array(jobs)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().rs_autotune_batched(arr, len(jobs), ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                                     _stream_handle(stream), cache_path.encode() if cache_path else None,
+                                     ctypes.byref(best)))
+    return best
+
+
+def release_graphs() -> None:
+    lib().rs_release_graphs()

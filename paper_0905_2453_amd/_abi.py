@@ -16,6 +16,7 @@ RS_ENOTFIT = -5
 RS_EINTERNAL = -6
 
 RS_FLAG_FAULT_INJECT = 0x1
+RS_FLAG_NO_GRAPH = 0x2
 
 
 class RayShootError(RuntimeError):
@@ -58,6 +59,12 @@ EXPORTS = [
     ("rs_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(Opts)]),
     ("rs_shoot", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                 ctypes.POINTER(Opts)]),
+    ("rs_batched_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.c_int32]),
+    ("rs_shoot_batched", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.POINTER(Opts)]),
+    ("rs_autotune_batched", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Opts)]),
+    ("rs_release_graphs", None, []),
 ]
 
 

@@ -47,23 +47,33 @@ __device__ __forceinline__ float4 pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
+template <int LT>
+struct TileSmem {
+    float4 lens[2][LT];
+    uint32_t win[kMaxWindow * kMaxWindow];
+    int cand[2][2 * kWaves];
+    uint32_t lost;
+};
+
+// Shoot ray tile `tile` of the job described by `a` with the whole workgroup; `slot` selects
+// the partial map the tile's counts go to.  Every thread of the workgroup must call it.
 template <int K1, int K2, int T, int LT, bool DUMP>
-__global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
+__device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, uint32_t slot, TileSmem<LT> &sm)
 {
     static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
     constexpr int PER = LT / kThreads;
     constexpr int R = K1 * K2;
     constexpr bool FOLD = K1 >= 2;  // fold m into shared differences when a lane has several columns
-    __shared__ float4 s_lens[2][LT];
-    __shared__ uint32_t s_win[kMaxWindow * kMaxWindow];
-    __shared__ int s_cand[2][2 * kWaves];
-    __shared__ uint32_t s_lost;
+    auto &s_lens = sm.lens;
+    auto &s_win = sm.win;
+    auto &s_cand = sm.cand;
+    auto &s_lost = sm.lost;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int tx = (int)(blockIdx.x % (uint32_t)a.tiles_x);
-    const int ty = (int)(blockIdx.x / (uint32_t)a.tiles_x);
+    const int tx = (int)(tile % (uint32_t)a.tiles_x);
+    const int ty = (int)(tile / (uint32_t)a.tiles_x);
     const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
     const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
 
@@ -250,7 +260,7 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 
     // Binning: runs of equal keys among consecutive lanes are added once (wave aggregation),
     // into the LDS window when the pixel falls inside it, else into this die's partial map.
-    uint32_t *part = a.partial + (size_t)(blockIdx.x & (kPartials - 1)) * (size_t)a.pstride;
+    uint32_t *part = a.partial + (size_t)slot * (size_t)a.pstride;
     uint32_t lost_cnt = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -285,6 +295,42 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     }
     if (tid == 0 && s_lost) atomicAdd(a.lost, (unsigned long long)s_lost);
 }
+
+template <int K1, int K2, int T, int LT, bool DUMP>
+__global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
+{
+    __shared__ TileSmem<LT> sm;
+    shoot_tile<K1, K2, T, LT, DUMP>(a, blockIdx.x, blockIdx.x & (kPartials - 1), sm);
+}
+
+// Persistent kernel over a table of jobs: each workgroup takes (job, tile) work items from an
+// atomic counter until none are left.  Items are numbered job by job in table order (the host
+// orders jobs by decreasing work per tile), so the costliest tiles are taken first.  Counts go
+// straight into each job's map.
+template <int K1, int K2, int T, int LT>
+__global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs b)
+{
+    __shared__ TileSmem<LT> sm;
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(b.queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= b.n_items) break;
+        // job j owns items [item_start[j], item_start[j+1])
+        int lo = 0, hi = b.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.item_start[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        shoot_tile<K1, K2, T, LT, false>(b.jobs[lo], item - b.item_start[lo], 0u, sm);
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v) { p[threadIdx.x] = v; }
 
 __global__ void __launch_bounds__(256) k_zero(uint4 *p, int64_t n4)
 {
@@ -348,6 +394,39 @@ hipError_t launch_k(const DirectArgs &a, int T, int LT, int64_t n_tiles, hipStre
 
 }  // namespace
 
+template <int K1, int K2>
+hipError_t launch_b(const BatchArgs &b, int T, int LT, int grid, hipStream_t s)
+{
+    if (LT == 256) {
+        if (T == 8) hipLaunchKernelGGL((k_batched<K1, K2, 8, 256>), dim3(grid), dim3(kThreads), 0, s, b);
+        else if (T == 16) hipLaunchKernelGGL((k_batched<K1, K2, 16, 256>), dim3(grid), dim3(kThreads), 0, s, b);
+        else if (T == 32) hipLaunchKernelGGL((k_batched<K1, K2, 32, 256>), dim3(grid), dim3(kThreads), 0, s, b);
+        else return hipErrorInvalidValue;
+    } else if (LT == 512) {
+        if (T == 8) hipLaunchKernelGGL((k_batched<K1, K2, 8, 512>), dim3(grid), dim3(kThreads), 0, s, b);
+        else if (T == 16) hipLaunchKernelGGL((k_batched<K1, K2, 16, 512>), dim3(grid), dim3(kThreads), 0, s, b);
+        else if (T == 32) hipLaunchKernelGGL((k_batched<K1, K2, 32, 512>), dim3(grid), dim3(kThreads), 0, s, b);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int K1, int K2>
+int occ_b(int T, int LT)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (LT == 256 && T == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 8, 256>, kThreads, 0);
+    if (LT == 256 && T == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 16, 256>, kThreads, 0);
+    if (LT == 256 && T == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 32, 256>, kThreads, 0);
+    if (LT == 512 && T == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 8, 512>, kThreads, 0);
+    if (LT == 512 && T == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 16, 512>, kThreads, 0);
+    if (LT == 512 && T == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<K1, K2, 32, 512>, kThreads, 0);
+    return e == hipSuccess ? n : 0;
+}
+
 bool ray_block_supported(int K1, int K2)
 {
     return (K1 == 1 && K2 == 4) || (K1 == 2 && K2 == 2) || (K1 == 2 && K2 == 4) || (K1 == 4 && K2 == 2) ||
@@ -364,6 +443,33 @@ hipError_t launch_direct(const DirectArgs &a, int K1, int K2, int T, int LT, int
     if (K1 == 4 && K2 == 4) return launch_k<4, 4>(a, T, LT, n_tiles, s);
     if (K1 == 2 && K2 == 8) return launch_k<2, 8>(a, T, LT, n_tiles, s);
     return hipErrorInvalidValue;
+}
+
+#define RS_BLOCK_SWITCH(FN, ...)                                              \
+    if (K1 == 1 && K2 == 4) return FN<1, 4>(__VA_ARGS__);                     \
+    if (K1 == 2 && K2 == 2) return FN<2, 2>(__VA_ARGS__);                     \
+    if (K1 == 2 && K2 == 4) return FN<2, 4>(__VA_ARGS__);                     \
+    if (K1 == 4 && K2 == 2) return FN<4, 2>(__VA_ARGS__);                     \
+    if (K1 == 4 && K2 == 4) return FN<4, 4>(__VA_ARGS__);                     \
+    if (K1 == 2 && K2 == 8) return FN<2, 8>(__VA_ARGS__);
+
+hipError_t launch_batched(const BatchArgs &b, int K1, int K2, int T, int LT, int grid, hipStream_t s)
+{
+    RS_BLOCK_SWITCH(launch_b, b, T, LT, grid, s)
+    return hipErrorInvalidValue;
+}
+
+int batched_occupancy(int K1, int K2, int T, int LT)
+{
+    RS_BLOCK_SWITCH(occ_b, T, LT)
+    return 0;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0 || n > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(n), 0, s, p, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s)

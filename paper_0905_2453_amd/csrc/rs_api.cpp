@@ -1,8 +1,17 @@
 // Host runtime of librs: argument validation, launch geometry and the C ABI (include/rs.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
 
 #include "rs_internal.h"
 
@@ -100,6 +109,262 @@ int64_t partial_stride(const rs_job *j)
     return (bins + 63) / 64 * 64;
 }
 
+// Device-side description of one job for a K1 x K2 ray block; counts go to `partial`.
+rs::DirectArgs make_args(const rs_job *job, const Tune &t, uint32_t *partial, int64_t pstride,
+                         const rs_opts *opts)
+{
+    const rs_raygrid &g = job->grid;
+    rs::DirectArgs a{};
+    a.lenses = reinterpret_cast<const float4 *>(job->lenses);
+    a.n_lens = job->n_lens;
+    a.glo1 = g.lo[0];
+    a.glo2 = g.lo[1];
+    a.gt1 = (g.hi[0] - g.lo[0]) / (double)g.n[0];
+    a.gt2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
+    a.wlo1 = g.win_lo[0];
+    a.wlo2 = g.win_lo[1];
+    a.wn1 = g.win_n[0];
+    a.wn2 = g.win_n[1];
+    a.lam1 = (1.0 - job->macro.gamma) - job->macro.kappa_c;
+    a.lam2 = (1.0 + job->macro.gamma) - job->macro.kappa_c;
+    a.mlo1 = job->map.lo[0];
+    a.mlo2 = job->map.lo[1];
+    a.ms1 = (double)job->map.n[0] / (job->map.hi[0] - job->map.lo[0]);
+    a.ms2 = (double)job->map.n[1] / (job->map.hi[1] - job->map.lo[1]);
+    a.mn1 = job->map.n[0];
+    a.mn2 = job->map.n[1];
+    a.window = t.W;
+    a.partial = partial;
+    a.pstride = pstride;
+    a.lost = reinterpret_cast<unsigned long long *>(job->n_lost);
+    a.ray_y = opts ? opts->ray_y : nullptr;
+    a.ray_pix = opts ? opts->ray_pix : nullptr;
+    const int64_t cols = 64 * (int64_t)t.K1;
+    const int64_t rows = (int64_t)rs::kWaves * t.K2;
+    a.tiles_x = (int32_t)((g.win_n[0] + cols - 1) / cols);
+    return a;
+}
+
+int64_t tile_count(const rs_job *job, const Tune &t)
+{
+    const int64_t cols = 64 * (int64_t)t.K1;
+    const int64_t rows = (int64_t)rs::kWaves * t.K2;
+    return ((job->grid.win_n[0] + cols - 1) / cols) * ((job->grid.win_n[1] + rows - 1) / rows);
+}
+
+// ---------------------------------------------------------------- batched launches
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    size_t queue_off, table_off, start_off, scratch_off, lost_off, total;
+};
+
+BatchLayout batch_layout(const rs_job *jobs, int32_t n_jobs)
+{
+    BatchLayout L{};
+    size_t off = 0;
+    L.queue_off = off;
+    off += 256;
+    L.table_off = off;
+    off += align256((size_t)n_jobs * sizeof(rs::DirectArgs));
+    L.start_off = off;
+    off += align256(((size_t)n_jobs + 1) * sizeof(uint32_t));
+    int64_t max_bins = 1;
+    for (int32_t j = 0; j < n_jobs; ++j)
+        max_bins = std::max<int64_t>(max_bins, (int64_t)jobs[j].map.n[0] * jobs[j].map.n[1]);
+    L.scratch_off = off;
+    off += align256((size_t)max_bins * sizeof(uint32_t));
+    L.lost_off = off;
+    off += 256;
+    L.total = off + 256;  // slack to align the caller's base pointer
+    return L;
+}
+
+std::mutex g_mu;
+// Host staging copies of uploaded job tables, kept alive per workspace address.
+std::map<void *, std::vector<uint8_t>> g_tables;
+
+struct GraphKey {
+    void *ws;
+    int device, K1, K2, T, LT, W, grid, n_jobs;
+    uint32_t n_items;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(ws, device, K1, K2, T, LT, W, grid, n_jobs, n_items) <
+               std::tie(o.ws, o.device, o.K1, o.K2, o.T, o.LT, o.W, o.grid, o.n_jobs, o.n_items);
+    }
+};
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+constexpr size_t kMaxGraphs = 32;
+
+struct PreparedBatch {
+    rs::BatchArgs args{};
+    uint64_t interactions = 0;  // ray-lens interactions of the items taken
+    int grid = 0;
+    int device = 0;
+};
+
+// Validate, order by decreasing work per tile, upload the job table into the workspace and fill
+// the kernel arguments.  With `scratch`, every job's counts and lost counter are redirected to a
+// scratch map inside the workspace (used by the autotuner).  At most `item_budget` ray-lens
+// interactions worth of items are taken (0 = all).
+int prepare_batch(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, const Tune &t,
+                  hipStream_t s, bool scratch, uint64_t item_budget, PreparedBatch &pb)
+{
+    if (n_jobs < 0) return fail(RS_EINVAL, "n_jobs < 0");
+    if (n_jobs > 0 && !jobs) return fail(RS_EINVAL, "jobs is NULL");
+    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const int st = validate_job(&jobs[j]);
+        if (st != RS_OK) {
+            char buf[512];
+            snprintf(buf, sizeof buf, "job %d: %s", j, g_err);
+            return fail(st, "%s", buf);
+        }
+    }
+    const BatchLayout L = batch_layout(jobs, n_jobs);
+    if (ws_bytes < L.total) return fail(RS_ESMALLBUF, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+
+    std::vector<int32_t> order(n_jobs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return jobs[a].n_lens > jobs[b].n_lens; });
+
+    const size_t table_bytes = (size_t)n_jobs * sizeof(rs::DirectArgs);
+    const size_t start_bytes = ((size_t)n_jobs + 1) * sizeof(uint32_t);
+    std::vector<uint8_t> host(table_bytes + start_bytes);
+    auto *args = reinterpret_cast<rs::DirectArgs *>(host.data());
+    auto *start = reinterpret_cast<uint32_t *>(host.data() + table_bytes);
+    uint64_t items = 0, taken = 0, inter = 0;
+    const uint64_t rays_per_tile = 64ull * (uint64_t)t.K1 * (uint64_t)rs::kWaves * (uint64_t)t.K2;
+    start[0] = 0;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const rs_job *job = &jobs[order[k]];
+        uint32_t *counts = job->counts;
+        if (scratch) {
+            rs_job tmp = *job;
+            tmp.counts = reinterpret_cast<uint32_t *>(base + L.scratch_off);
+            tmp.n_lost = reinterpret_cast<uint64_t *>(base + L.lost_off);
+            args[k] = make_args(&tmp, t, tmp.counts, 0, nullptr);
+        } else {
+            args[k] = make_args(job, t, counts, 0, nullptr);
+        }
+        const int64_t nt = tile_count(job, t);
+        items += (uint64_t)nt;
+        if (items >= (uint64_t(1) << 31)) return fail(RS_ERANGE, "more than 2^31 ray tiles in one batch");
+        start[k + 1] = (uint32_t)items;
+        for (int64_t i = 0; i < nt; ++i) {
+            if (item_budget && inter >= item_budget) break;
+            inter += rays_per_tile * (uint64_t)job->n_lens;
+            ++taken;
+        }
+    }
+    if (!item_budget) taken = items;
+
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return dev_fail(e, "device query");
+    const int occ = rs::batched_occupancy(t.K1, t.K2, t.T, t.LT);
+    if (occ <= 0) return fail(RS_EINTERNAL, "no occupancy for the batched kernel");
+
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        std::vector<uint8_t> &keep = g_tables[workspace];
+        keep.swap(host);
+        if (table_bytes) {
+            e = hipMemcpyAsync(base + L.table_off, keep.data(), table_bytes, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return dev_fail(e, "job table upload");
+        }
+        e = hipMemcpyAsync(base + L.start_off, keep.data() + table_bytes, start_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return dev_fail(e, "job table upload");
+    }
+    pb.args.jobs = reinterpret_cast<const rs::DirectArgs *>(base + L.table_off);
+    pb.args.item_start = reinterpret_cast<const uint32_t *>(base + L.start_off);
+    pb.args.n_jobs = n_jobs;
+    pb.args.n_items = (uint32_t)taken;
+    pb.args.queue = reinterpret_cast<uint32_t *>(base + L.queue_off);
+    pb.interactions = item_budget ? inter : 0;
+    pb.grid = (int)std::min<uint64_t>(std::max<uint64_t>(taken, 1), (uint64_t)cus * (uint64_t)occ);
+    pb.device = dev;
+    return RS_OK;
+}
+
+// Reset the work counter and run the persistent kernel, captured once into a graph per
+// (workspace, shape, grid, batch size) and replayed afterwards; the legacy default stream cannot
+// be captured, so there the two kernels are launched directly.
+int run_batch(const PreparedBatch &pb, const Tune &t, void *workspace, hipStream_t s, bool use_graph)
+{
+    if (pb.args.n_items == 0) return RS_OK;
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = rs::launch_fill_u32(pb.args.queue, 1, 0u, s);
+        if (e == hipSuccess) e = rs::launch_batched(pb.args, t.K1, t.K2, t.T, t.LT, pb.grid, s);
+        return e;
+    };
+    if (!use_graph || s == nullptr) {
+        const hipError_t e = enqueue();
+        return e == hipSuccess ? RS_OK : dev_fail(e, "batched launch");
+    }
+    const GraphKey key{workspace, pb.device, t.K1, t.K2, t.T, t.LT, t.W, pb.grid, pb.args.n_jobs, pb.args.n_items};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) exec = it->second;
+    }
+    if (!exec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return dev_fail(e, "begin capture");
+        const hipError_t el = enqueue();
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (el != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return dev_fail(el, "batched launch (capture)");
+        }
+        if (e != hipSuccess) return dev_fail(e, "end capture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return dev_fail(e, "graph instantiate");
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_graphs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(g_graphs.begin()->second);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs[key] = exec;
+    }
+    const hipError_t e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? RS_OK : dev_fail(e, "graph launch");
+}
+
+std::string tune_key(const rs_job *jobs, int32_t n_jobs)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::vector<double> nl, rays, bins;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        nl.push_back(std::log2(1.0 + (double)jobs[j].n_lens));
+        rays.push_back(std::log2(1.0 + (double)jobs[j].grid.win_n[0] * (double)jobs[j].grid.win_n[1]));
+        bins.push_back(std::log2(1.0 + (double)jobs[j].map.n[0] * (double)jobs[j].map.n[1]));
+    }
+    auto med = [](std::vector<double> v) {
+        if (v.empty()) return 0L;
+        std::sort(v.begin(), v.end());
+        return (long)std::lround(v[v.size() / 2]);
+    };
+    std::ostringstream o;
+    o << arch << "|lens2^" << med(nl) << "|rays2^" << med(rays) << "|map2^" << med(bins);
+    return o.str();
+}
+
 }  // namespace
 
 extern "C" {
@@ -147,48 +412,138 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
     uint32_t *part = reinterpret_cast<uint32_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     const int64_t pstride = partial_stride(job);
     const int64_t bins = (int64_t)job->map.n[0] * job->map.n[1];
-
-    rs::DirectArgs a{};
-    a.lenses = reinterpret_cast<const float4 *>(job->lenses);
-    a.n_lens = job->n_lens;
-    a.glo1 = g.lo[0];
-    a.glo2 = g.lo[1];
-    a.gt1 = (g.hi[0] - g.lo[0]) / (double)g.n[0];
-    a.gt2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
-    a.wlo1 = g.win_lo[0];
-    a.wlo2 = g.win_lo[1];
-    a.wn1 = g.win_n[0];
-    a.wn2 = g.win_n[1];
-    a.lam1 = (1.0 - job->macro.gamma) - job->macro.kappa_c;
-    a.lam2 = (1.0 + job->macro.gamma) - job->macro.kappa_c;
-    a.mlo1 = job->map.lo[0];
-    a.mlo2 = job->map.lo[1];
-    a.ms1 = (double)job->map.n[0] / (job->map.hi[0] - job->map.lo[0]);
-    a.ms2 = (double)job->map.n[1] / (job->map.hi[1] - job->map.lo[1]);
-    a.mn1 = job->map.n[0];
-    a.mn2 = job->map.n[1];
-    a.window = t.W;
-    a.partial = part;
-    a.pstride = pstride;
-    a.lost = reinterpret_cast<unsigned long long *>(job->n_lost);
-    a.ray_y = opts ? opts->ray_y : nullptr;
-    a.ray_pix = opts ? opts->ray_pix : nullptr;
-
-    const int64_t cols = 64 * (int64_t)t.K1;
-    const int64_t tiles_x = (g.win_n[0] + cols - 1) / cols;
-    const int64_t rows = (int64_t)rs::kWaves * t.K2;
-    const int64_t tiles_y = (g.win_n[1] + rows - 1) / rows;
-    if (tiles_x * tiles_y >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
-    a.tiles_x = (int32_t)tiles_x;
+    const rs::DirectArgs a = make_args(job, t, part, pstride, opts);
+    const int64_t n_tiles = tile_count(job, t);
+    if (n_tiles >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = rs::launch_zero(part, rs::kPartials * pstride, s);
     if (e != hipSuccess) return dev_fail(e, "zero partial maps");
-    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, tiles_x * tiles_y, s);
+    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, n_tiles, s);
     if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");
     return RS_OK;
+}
+
+size_t rs_batched_workspace_bytes(const rs_job *jobs, int32_t n_jobs)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
+    for (int32_t j = 0; j < n_jobs; ++j)
+        if (validate_job(&jobs[j]) != RS_OK) return 0;
+    return batch_layout(jobs, n_jobs).total;
+}
+
+int rs_shoot_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, void *stream,
+                     const rs_opts *opts)
+{
+    g_err[0] = '\0';
+    Tune t;
+    int st = resolve_opts(opts, t);
+    if (st != RS_OK) return st;
+    if (opts && (opts->ray_y || opts->ray_pix)) return fail(RS_EINVAL, "per-ray dumps are not available in batches");
+    if (opts && (opts->flags & RS_FLAG_FAULT_INJECT)) {
+        // validate first so the injected fault only stands for device failures
+        if (n_jobs < 0 || (n_jobs > 0 && !jobs) || !workspace) return fail(RS_EINVAL, "bad batch arguments");
+        return fail(RS_EDEVICE, "injected fault (RS_FLAG_FAULT_INJECT)");
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    PreparedBatch pb;
+    st = prepare_batch(jobs, n_jobs, workspace, ws_bytes, t, s, false, 0, pb);
+    if (st != RS_OK) return st;
+    const bool graph = !(opts && (opts->flags & RS_FLAG_NO_GRAPH));
+    return run_batch(pb, t, workspace, s, graph);
+}
+
+int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, void *stream,
+                        const char *cache_path, rs_opts *best)
+{
+    g_err[0] = '\0';
+    if (!best) return fail(RS_EINVAL, "best is NULL");
+    Tune base;
+    int st = resolve_opts(best, base);
+    if (st != RS_OK) return st;
+    if (n_jobs <= 0 || !jobs) return fail(RS_EINVAL, "need at least one job");
+    for (int32_t j = 0; j < n_jobs; ++j)
+        if ((st = validate_job(&jobs[j])) != RS_OK) return st;
+    const std::string key = tune_key(jobs, n_jobs);
+    if (cache_path && *cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        bool found = false;
+        int K1 = 0, K2 = 0, LT = 0, W = 0;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int a, b, c, d;
+            if ((ls >> k >> a >> b >> c >> d) && k == key && rs::ray_block_supported(a, b)) {
+                K1 = a; K2 = b; LT = c; W = d; found = true;
+            }
+        }
+        if (found) {
+            best->block_cols = K1;
+            best->block_rows = K2;
+            best->lens_tile = LT;
+            best->map_window = W == 0 ? -1 : W;
+            return RS_OK;
+        }
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int shapes[][2] = {{1, 4}, {2, 4}, {4, 4}, {2, 8}};
+    const int windows[] = {32, 64};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return dev_fail(e, "event create");
+    double best_rate = -1.0;
+    Tune win = base;
+    const uint64_t budget = 200000000000ull;  // ~30 ms of work per candidate
+    for (const auto &sh : shapes) {
+        for (int W : windows) {
+            Tune t = base;
+            t.K1 = sh[0];
+            t.K2 = sh[1];
+            t.W = W;
+            PreparedBatch pb;
+            st = prepare_batch(jobs, n_jobs, workspace, ws_bytes, t, s, true, budget, pb);
+            if (st != RS_OK) break;
+            if ((st = run_batch(pb, t, workspace, s, false)) != RS_OK) break;  // warm-up
+            e = hipEventRecord(e0, s);
+            for (int r = 0; r < 2 && e == hipSuccess && st == RS_OK; ++r) st = run_batch(pb, t, workspace, s, false);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess || st != RS_OK) break;
+            const double rate = 2.0 * (double)pb.interactions / std::max(1e-3, (double)ms);
+            if (rate > best_rate) {
+                best_rate = rate;
+                win = t;
+            }
+        }
+        if (e != hipSuccess || st != RS_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(e, "autotune timing");
+    if (st != RS_OK) return st;
+    best->block_cols = win.K1;
+    best->block_rows = win.K2;
+    best->lens_tile = win.LT;
+    best->map_window = win.W == 0 ? -1 : win.W;
+    if (cache_path && *cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << ' ' << win.K1 << ' ' << win.K2 << ' ' << win.LT << ' ' << win.W << '\n';
+    }
+    return RS_OK;
+}
+
+void rs_release_graphs(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+    g_tables.clear();
 }
 
 }  // extern "C"

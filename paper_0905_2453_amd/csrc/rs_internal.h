@@ -36,11 +36,26 @@ struct DirectArgs {
     int32_t *ray_pix;
 };
 
+// A table of jobs for the persistent batched kernel (all in device memory).
+struct BatchArgs {
+    const DirectArgs *jobs;     // n_jobs descriptors
+    const uint32_t *item_start; // n_jobs + 1 prefix sums of ray tiles per job
+    int32_t n_jobs;
+    uint32_t n_items;           // work items to take this launch (<= item_start[n_jobs])
+    uint32_t *queue;            // work-item counter, zeroed before each launch
+};
+
 // Per-lane ray blocks (K1 columns x K2 rows) compiled into the library.
 bool ray_block_supported(int K1, int K2);
 // Launch the direct-sum kernel for a K1 x K2 ray block per lane, T-lens float32 runs and LT-lens
 // LDS tiles.
 hipError_t launch_direct(const DirectArgs &a, int K1, int K2, int T, int LT, int64_t n_tiles, hipStream_t s);
+// Launch the persistent batched kernel on `grid` workgroups.
+hipError_t launch_batched(const BatchArgs &b, int K1, int K2, int T, int LT, int grid, hipStream_t s);
+// Resident workgroups per compute unit of the batched kernel (0 on error).
+int batched_occupancy(int K1, int K2, int T, int LT);
+// p[0..n) = v with a one-block kernel (graph-capture safe, n <= 1024).
+hipError_t launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
 // Zero the partial maps (fill kernel; graph-capture safe).
 hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s);
 // counts[b] += sum_s partial[s * pstride + b] for b < bins.

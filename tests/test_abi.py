@@ -161,3 +161,27 @@ def test_fault_injection_reports_device_error_without_launch():
 def test_version_string():
     P, L = _lib()
     assert b"gfx950" in L.rs_version()
+
+
+def test_batched_validation_without_device():
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    good = _job()
+    bad = _job(n_lens=-1)
+    arr = (_abi.Job * 2)(good, bad)
+    assert L.rs_batched_workspace_bytes(arr, 2) == 0
+    arr_ok = (_abi.Job * 2)(good, good)
+    need = L.rs_batched_workspace_bytes(arr_ok, 2)
+    assert need > 0
+    # invalid job is reported with its index before any HIP call
+    st = L.rs_shoot_batched(arr, 2, ctypes.c_void_p(0x4000), 1 << 30, None, None)
+    assert st == -1 and b"job 1" in L.rs_last_error()
+    assert L.rs_shoot_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need - 1, None, None) == -4
+    assert L.rs_shoot_batched(arr_ok, -1, ctypes.c_void_p(0x4000), need, None, None) == -1
+    o = _abi.Opts()
+    o.ray_y, o.ray_pix = 0x10, 0x20
+    assert L.rs_shoot_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need, None, ctypes.byref(o)) == -1
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    assert L.rs_shoot_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need, None, ctypes.byref(o)) == -3
+    assert L.rs_autotune_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need, None, None, None) == -1

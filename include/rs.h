@@ -109,6 +109,7 @@ typedef struct {
 /* Flags for rs_opts.flags */
 #define RS_FLAG_FAULT_INJECT 0x1u  /* fail with RS_EDEVICE after validation, before any HIP call */
 #define RS_FLAG_NO_GRAPH 0x2u      /* rs_shoot_batched: launch directly instead of replaying a graph */
+#define RS_FLAG_AFFINE_ONLY 0x4u   /* rs_farfield_eval: far field from the affine base alone (ablation) */
 
 /*
  * Tuning and diagnostics for rs_shoot.  NULL, or a zero field, selects the
@@ -176,6 +177,63 @@ int rs_shoot_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t
  */
 int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes, void *stream,
                         const char *cache_path, rs_opts *best);
+
+/*
+ * Learned far-field closure.  The ray window is cut into tiles of tile_rays[0] x tile_rays[1]
+ * rays.  For each tile the lenses closer than r_near to the tile rectangle (the rectangle
+ * covered by its ray cells; FP64 distance) are the near set, summed exactly per ray; the sum
+ * over all other lenses (the far field, eq. 2 restricted to a lens subset as in eq. 5) is
+ * replaced by
+ *     alpha_far(c) + J_far(c) (x - c) + s_t * net((x - c) / h)
+ * with c, h the tile centre and half-widths, alpha_far(c) and its Jacobian J_far(c) exact in
+ * FP64, and net a 2 -> 16 -> 64 -> 64 -> 2 network (features sin, cos of (pi/2) 2^k u_d,
+ * k = 0..3; SiLU) trained per tile on the far-field residual at n_samples exact samples
+ * (float32 direct sums with FP64 combination, like rs_shoot), normalised by its RMS s_t.
+ * Training: mini-batch Adam (0.9, 0.999, 1e-8), step t uses samples [(t-1) batch mod
+ * n_samples, +batch), learning rate lr (1 + cos(pi (t-1) / steps)) / 2; GEMM operands in
+ * bfloat16, sums in FP32, master weights FP32.
+ */
+typedef struct {
+    int32_t tile_rays[2];       /* rays per tile along each axis, e.g. 64 x 64                    */
+    double r_near;              /* near radius (Einstein radii), e.g. 8                            */
+    int32_t n_samples;          /* fit samples per tile, multiple of 1024, e.g. 4096                */
+    int32_t steps;              /* Adam steps (0 = keep the initial parameters), e.g. 2000          */
+    int32_t batch;              /* samples per step: multiple of 128 dividing n_samples, e.g. 512   */
+    float lr;                   /* peak learning rate, e.g. 1e-2                                    */
+    double cell_size;           /* lens cell side for the near-set search (0 = r_near / 4)          */
+    const float *samples;       /* device, n_samples x 2 tile-local points in [-1,1]^2 (input)       */
+    const float *init_params;   /* device, 5378 initial parameters, the same for every tile (input) */
+    float *debug_grad;          /* device, nullable: n_tiles x 5378, gradient of the first step      */
+    float *debug_targets;       /* device, nullable: n_tiles x n_samples x 2 residual samples        */
+} rs_ff_config;
+
+/*
+ * Model buffer (device, 256-byte aligned): a 256-byte header (magic, configuration hash, tile
+ * counts) then one record per tile (tile index ty * tiles_x + tx) of rs_farfield_model_bytes /
+ * n_tiles bytes: 10 doubles (c1, c2, h1, h2, alpha_far(c) 1, 2, J11, J12, J22, s_t) padded to
+ * 128 bytes, the 5378 parameters as bfloat16 (W1 [64][16], b1, W2 [64][64], b2, W3 [2][64], b3)
+ * padded to 16 bytes, then b1, b2, b3 again as 130 floats.  The hash covers the ray grid,
+ * window, tiling, fit settings and lens count (not the lens positions).
+ */
+size_t rs_farfield_model_bytes(const rs_job *job, const rs_ff_config *cfg);
+size_t rs_farfield_fit_workspace_bytes(const rs_job *job, const rs_ff_config *cfg);
+size_t rs_farfield_eval_workspace_bytes(const rs_job *job, const rs_ff_config *cfg);
+
+/*
+ * Fit every tile's closure: affine base, exact far-field samples, normalisation, training.
+ * job->counts / n_lost are not touched.  Asynchronous on `stream`.
+ */
+int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, size_t model_bytes, void *workspace,
+                    size_t ws_bytes, void *stream);
+
+/*
+ * Shoot the job's ray window with the fitted closure and add the counts to job->counts and
+ * job->n_lost (same pixel rules as rs_shoot).  opts: ray_y / ray_pix dumps and
+ * RS_FLAG_AFFINE_ONLY (network off: the method without the learned part).  Reads the model
+ * header first (synchronises the stream) and returns RS_ENOTFIT on a mismatch.
+ */
+int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
+                     void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
 
 /* Destroy the cached batch graphs and staged job tables (e.g. before freeing workspaces). */
 void rs_release_graphs(void);

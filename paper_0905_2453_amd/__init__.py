@@ -175,3 +175,68 @@ def autotune_batched(jobs, workspace, cache_path: str | None = None, opts: Opts 
 
 def release_graphs() -> None:
     lib().rs_release_graphs()
+
+
+# ---------------------------------------------------------------- learned far field
+
+FFConfig = _abi.FFConfig
+
+
+def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, batch=512, lr=1e-2,
+              cell_size=0.0, debug_grad=None, debug_targets=None) -> FFConfig:
+    """rs_ff_config from device tensors: samples (n x 2 float32 in [-1,1]^2), init_params (5378 float32)."""
+    torch = _torch()
+    _require_cuda(samples, "samples", torch.float32)
+    _require_cuda(init_params, "init_params", torch.float32)
+    if samples.dim() != 2 or samples.shape[1] != 2:
+        raise ValueError("samples must be n x 2")
+    if init_params.numel() != _abi.N_PARAMS:
+        raise ValueError(f"init_params must hold {_abi.N_PARAMS} values")
+    c = FFConfig()
+    c.tile_rays[0], c.tile_rays[1] = int(tile_rays[0]), int(tile_rays[1])
+    c.r_near = float(r_near)
+    c.n_samples = int(samples.shape[0])
+    c.steps, c.batch, c.lr, c.cell_size = int(steps), int(batch), float(lr), float(cell_size)
+    c.samples = samples.data_ptr()
+    c.init_params = init_params.data_ptr()
+    c.debug_grad = debug_grad.data_ptr() if debug_grad is not None else None
+    c.debug_targets = debug_targets.data_ptr() if debug_targets is not None else None
+    return c
+
+
+def _size(fn, job, cfg):
+    n = fn(ctypes.byref(job), ctypes.byref(cfg))
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+def farfield_model_bytes(job, cfg) -> int:
+    return _size(lib().rs_farfield_model_bytes, job, cfg)
+
+
+def farfield_fit_workspace_bytes(job, cfg) -> int:
+    return _size(lib().rs_farfield_fit_workspace_bytes, job, cfg)
+
+
+def farfield_eval_workspace_bytes(job, cfg) -> int:
+    return _size(lib().rs_farfield_eval_workspace_bytes, job, cfg)
+
+
+def farfield_fit(job, cfg, model, workspace, stream=None) -> None:
+    """rs_farfield_fit: fill `model` (uint8 device tensor) with every tile's fitted closure."""
+    _require_cuda(model, "model")
+    _require_cuda(workspace, "workspace")
+    _check(lib().rs_farfield_fit(ctypes.byref(job), ctypes.byref(cfg), ctypes.c_void_p(model.data_ptr()),
+                                 model.numel() * model.element_size(), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+
+
+def farfield_eval(job, cfg, model, workspace, opts: Opts | None = None, stream=None) -> None:
+    """rs_farfield_eval: shoot the job's rays with the fitted closure, adding into the job's map."""
+    _require_cuda(model, "model")
+    _require_cuda(workspace, "workspace")
+    _check(lib().rs_farfield_eval(ctypes.byref(job), ctypes.byref(cfg), ctypes.c_void_p(model.data_ptr()),
+                                  model.numel() * model.element_size(), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel() * workspace.element_size(), _stream_handle(stream),
+                                  ctypes.byref(opts) if opts else None))

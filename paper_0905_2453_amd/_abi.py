@@ -17,6 +17,8 @@ RS_EINTERNAL = -6
 
 RS_FLAG_FAULT_INJECT = 0x1
 RS_FLAG_NO_GRAPH = 0x2
+RS_FLAG_AFFINE_ONLY = 0x4
+N_PARAMS = 5378
 
 
 class RayShootError(RuntimeError):
@@ -51,6 +53,13 @@ class Opts(ctypes.Structure):
                 ("ray_pix", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
+class FFConfig(ctypes.Structure):
+    _fields_ = [("tile_rays", c_int32_2), ("r_near", ctypes.c_double), ("n_samples", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("cell_size", ctypes.c_double), ("samples", ctypes.c_void_p), ("init_params", ctypes.c_void_p),
+                ("debug_grad", ctypes.c_void_p), ("debug_targets", ctypes.c_void_p)]
+
+
 # (name, restype, argtypes) of every exported function
 EXPORTS = [
     ("rs_status_str", ctypes.c_char_p, [ctypes.c_int]),
@@ -64,6 +73,14 @@ EXPORTS = [
                                         ctypes.c_void_p, ctypes.POINTER(Opts)]),
     ("rs_autotune_batched", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Opts)]),
+    ("rs_farfield_model_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig)]),
+    ("rs_farfield_fit_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig)]),
+    ("rs_farfield_eval_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig)]),
+    ("rs_farfield_fit", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig), ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("rs_farfield_eval", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig), ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(Opts)]),
     ("rs_release_graphs", None, []),
 ]
 

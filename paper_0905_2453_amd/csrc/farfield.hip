@@ -1,0 +1,800 @@
+// Learned far-field closure on gfx950.
+//
+// The deflection of a ray (Thompson et al. 2009, section 1 eq. 2) is split per ray tile into
+// a near part, summed exactly over the lenses closer than r_near to the tile rectangle, and a
+// far part (the rest of the sum, the lens subsets of section 2 eq. 5).  The far part is
+// represented per tile by an exact FP64 affine base at the tile centre plus a small network
+// fitted to exact far-field sums:
+//   alpha_far(x) ~ alpha_far(c) + J_far(c) (x - c) + s_t * net((x - c) / h)
+// net: 16 Fourier features -> 64 -> 64 -> 2 (SiLU), bfloat16 GEMM operands, FP32 sums.
+//
+// Hidden-unit layout.  A 32x32x16 MFMA leaves in lane l (half hf = l / 32, column l % 32) the
+// output rows 32 T + 8 (r / 4) + 4 hf + r % 4 of tile T, register r.  The rows of every weight
+// matrix that produces hidden units are permuted (perm_row) so that register r of tile T holds
+// hidden unit slot_unit(16 T + r, hf): exactly the B-operand layout of the next 32x32x16 MFMA
+// over hidden units.  So each lane keeps the 32 hidden values of its sample it needs, and the
+// forward pass and the data half of the backward pass need no cross-lane moves.  The weight
+// gradients contract over samples and go through small per-wave LDS transposes.
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+
+using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
+using u16x8 = unsigned short __attribute__((ext_vector_type(8)));
+using f32x16 = float __attribute__((ext_vector_type(16)));
+using f32x4 = float __attribute__((ext_vector_type(4)));
+
+constexpr double kRcpBiasComp = 1.0 + 6.41e-9;  // see direct.hip: mean bias of v_rcp_f32
+constexpr float kPadCoord = 1.0e18f;
+
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t *p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p));
+}
+__device__ __forceinline__ bf16x8 pack8(const uint16_t *a)
+{
+    u16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = a[i];
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// logical hidden unit produced by output row R (0..63) of a hidden-producing layer
+__device__ __forceinline__ int perm_row(int R)
+{
+    const int T = R >> 5, rr = R & 31, a = rr >> 3, hf = (rr >> 2) & 1, b = rr & 3;
+    return 32 * T + 16 * (a >> 1) + 8 * hf + 4 * (a & 1) + b;
+}
+// logical hidden unit held in slot q (0..31) by a lane of half hf
+__device__ __forceinline__ int slot_unit(int q, int hf) { return 16 * (q >> 3) + 8 * hf + (q & 7); }
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Lens (FP32 record) within r_near of the tile rectangle, decided in FP64.
+__device__ __forceinline__ bool is_near(float lx, float ly, const double lo[2], const double hi[2], double rn2)
+{
+    const double x = lx, y = ly;
+    const double ex = fmax(fmax(lo[0] - x, x - hi[0]), 0.0);
+    const double ey = fmax(fmax(lo[1] - y, y - hi[1]), 0.0);
+    return ex * ex + ey * ey < rn2;
+}
+
+__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i)
+{
+    double v = ((double)i + 0.5) * t;
+    double w = lo + v;
+    return (float)w;
+}
+
+// Tile rectangle (cells of the tile's rays), centre and half-widths.
+__device__ __forceinline__ void tile_geom(const FarArgs &f, uint32_t tile, double lo[2], double hi[2], double c[2],
+                                          double hw[2], int64_t i0[2], int n[2])
+{
+    const int tx = (int)(tile % (uint32_t)f.tiles_x), ty = (int)(tile / (uint32_t)f.tiles_x);
+    i0[0] = f.wlo1 + (int64_t)tx * f.TX;
+    i0[1] = f.wlo2 + (int64_t)ty * f.TY;
+    n[0] = (int)min((int64_t)f.TX, f.wlo1 + f.wn1 - i0[0]);
+    n[1] = (int)min((int64_t)f.TY, f.wlo2 + f.wn2 - i0[1]);
+    lo[0] = f.glo1 + (double)i0[0] * f.gt1;
+    lo[1] = f.glo2 + (double)i0[1] * f.gt2;
+    hi[0] = f.glo1 + (double)(i0[0] + n[0]) * f.gt1;
+    hi[1] = f.glo2 + (double)(i0[1] + n[1]) * f.gt2;
+    c[0] = 0.5 * (lo[0] + hi[0]);
+    c[1] = 0.5 * (lo[1] + hi[1]);
+    hw[0] = 0.5 * (hi[0] - lo[0]);
+    hw[1] = 0.5 * (hi[1] - lo[1]);
+}
+
+__device__ __forceinline__ double *tile_hdr(const FarArgs &f, uint32_t tile)
+{
+    return reinterpret_cast<double *>(f.model + kModelHeader + (size_t)tile * kTileRecord);
+}
+__device__ __forceinline__ uint16_t *tile_w(const FarArgs &f, uint32_t tile)
+{
+    return reinterpret_cast<uint16_t *>(f.model + kModelHeader + (size_t)tile * kTileRecord + kTileWeightsOff);
+}
+
+// Features of one axis for a lane: phi[8 hf + 2k] = sin(w_k u), phi[8 hf + 2k + 1] = cos(w_k u),
+// w_k = (pi / 2) 2^k, rounded to bfloat16.
+__device__ __forceinline__ void features8(float u, uint16_t *out)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float s, co;
+        sincosf(1.57079632679489662f * (float)(1 << k) * u, &s, &co);
+        out[2 * k] = to_bf16(s);
+        out[2 * k + 1] = to_bf16(co);
+    }
+}
+
+// Forward pass of 32 samples (one per lane pair) through layers 1 and 2: returns z1, z2 and
+// the bfloat16 activations h1, h2 in the slot layout, and the network output (both lanes).
+struct Fwd {
+    float z1[32], z2[32];
+    uint16_t h1[32], h2[32];
+    float o[2];
+};
+
+__device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint16_t *phi8, int lane,
+                                          Fwd &r)
+{
+    const int hf = lane >> 5, col = lane & 31;
+    const bf16x8 bphi = pack8(phi8);
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        const int R = 32 * T + col;
+        const bf16x8 a = lds8(Wbf + kOffW1 + perm_row(R) * 16 + 8 * hf);
+        f32x16 acc = {};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bphi, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const float z = acc[q] + sbias[slot_unit(16 * T + q, hf)];
+            r.z1[16 * T + q] = z;
+            r.h1[16 * T + q] = to_bf16(z * sigm(z));
+        }
+    }
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        const int R = 32 * T + col;
+        f32x16 acc = {};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const bf16x8 a = lds8(Wbf + kOffW2 + perm_row(R) * 64 + 16 * kk + 8 * hf);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(r.h1 + 8 * kk), acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const float z = acc[q] + sbias[64 + slot_unit(16 * T + q, hf)];
+            r.z2[16 * T + q] = z;
+            r.h2[16 * T + q] = to_bf16(z * sigm(z));
+        }
+    }
+    float po0 = 0.f, po1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int u = slot_unit(q, hf);
+        const float h = from_bf16(r.h2[q]);
+        po0 = fmaf(from_bf16(Wbf[kOffW3 + u]), h, po0);
+        po1 = fmaf(from_bf16(Wbf[kOffW3 + 64 + u]), h, po1);
+    }
+    // the two halves of a sample live in lanes l and l ^ 32; add them in a fixed order
+    const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
+    r.o[0] = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
+    r.o[1] = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
+}
+
+// ---------------------------------------------------------------- fit: affine base
+
+__global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
+{
+    __shared__ double red[4][256];
+    const uint32_t tile = blockIdx.x;
+    double lo[2], hi[2], c[2], hw[2];
+    int64_t i0[2];
+    int n[2];
+    tile_geom(f, tile, lo, hi, c, hw, i0, n);
+    const double rn2 = f.r_near * f.r_near;
+    double a1 = 0, a2 = 0, j11 = 0, j12 = 0;
+    for (int64_t i = threadIdx.x; i < f.n_lens; i += 256) {
+        const float4 l = f.lenses[i];
+        if (is_near(l.x, l.y, lo, hi, rn2)) continue;
+        const double dx = c[0] - (double)l.x, dy = c[1] - (double)l.y, m = l.z;
+        const double r2 = dx * dx + dy * dy;
+        const double q = m / r2, q2 = q / r2;
+        a1 += q * dx;
+        a2 += q * dy;
+        j11 += q2 * (dy * dy - dx * dx);
+        j12 += -2.0 * q2 * dx * dy;
+    }
+    red[0][threadIdx.x] = a1;
+    red[1][threadIdx.x] = a2;
+    red[2][threadIdx.x] = j11;
+    red[3][threadIdx.x] = j12;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *h = tile_hdr(f, tile);
+        h[0] = c[0];
+        h[1] = c[1];
+        h[2] = hw[0];
+        h[3] = hw[1];
+        h[4] = red[0][0];
+        h[5] = red[1][0];
+        h[6] = red[2][0];
+        h[7] = red[3][0];
+        h[8] = -red[2][0];
+        h[9] = 1.0;
+    }
+}
+
+// ---------------------------------------------------------------- fit: exact far-field samples
+
+// Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024).
+// Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
+// of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
+__global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
+{
+    constexpr int LT = 256, T = 16, S = 4;
+    __shared__ float4 s_lens[2][LT];
+    const uint32_t tile = blockIdx.x / (uint32_t)f.parts, part = blockIdx.x % (uint32_t)f.parts;
+    double lo[2], hi[2], c[2], hw[2];
+    int64_t i0[2];
+    int n[2];
+    tile_geom(f, tile, lo, hi, c, hw, i0, n);
+    const double rn2 = f.r_near * f.r_near;
+    const int tid = threadIdx.x;
+    float px[S], py[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int si = part * 1024 + k * 256 + tid;
+        px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]);
+        py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]);
+    }
+    double A1[S] = {}, A2[S] = {};
+    auto fetch = [&](int64_t i) -> float4 {
+        if (i >= f.n_lens) return make_float4(kPadCoord, kPadCoord, 0.f, 0.f);
+        const float4 l = f.lenses[i];
+        return is_near(l.x, l.y, lo, hi, rn2) ? make_float4(kPadCoord, kPadCoord, 0.f, 0.f) : l;
+    };
+    const int64_t n_tiles = (f.n_lens + LT - 1) / LT;
+    float4 reg = n_tiles > 0 ? fetch(tid) : make_float4(0, 0, 0, 0);
+    if (n_tiles > 0) s_lens[0][tid] = reg;
+    __syncthreads();
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        const int buf = (int)(t & 1);
+        const bool more = t + 1 < n_tiles;
+        if (more) reg = fetch((t + 1) * LT + tid);
+        const float4 *L = s_lens[buf];
+        for (int r = 0; r < LT; r += T) {
+            float s1[S], s2[S];
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                const float4 l = L[r + j];
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const float dx = px[k] - l.x, dy = py[k] - l.y;
+                    const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                    s1[k] = j == 0 ? d * dx : fmaf(d, dx, s1[k]);
+                    s2[k] = j == 0 ? d * dy : fmaf(d, dy, s2[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                A1[k] += (double)s1[k];
+                A2[k] += (double)s2[k];
+            }
+        }
+        if (more) s_lens[buf ^ 1][tid] = reg;
+        __syncthreads();
+    }
+    const double *h = tile_hdr(f, tile);
+    const double a01 = h[4], a02 = h[5], j11 = h[6], j12 = h[7], j22 = h[8];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int si = part * 1024 + k * 256 + tid;
+        const double d1 = (double)px[k] - c[0], d2 = (double)py[k] - c[1];
+        const double r1 = A1[k] * kRcpBiasComp - (a01 + j11 * d1 + j12 * d2);
+        const double r2 = A2[k] * kRcpBiasComp - (a02 + j12 * d1 + j22 * d2);
+        float *out = f.targets + ((size_t)tile * f.n_samples + si) * 2;
+        out[0] = (float)r1;
+        out[1] = (float)r2;
+        if (f.debug_targets) {
+            float *dbg = f.debug_targets + ((size_t)tile * f.n_samples + si) * 2;
+            dbg[0] = (float)r1;
+            dbg[1] = (float)r2;
+        }
+    }
+}
+
+// Per tile: s_t = RMS of the residual samples (both components); targets /= s_t.
+__global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
+{
+    __shared__ double red[256];
+    const uint32_t tile = blockIdx.x;
+    float *t = f.targets + (size_t)tile * f.n_samples * 2;
+    double s = 0;
+    for (int i = threadIdx.x; i < 2 * f.n_samples; i += 256) s += (double)t[i] * (double)t[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    double st = sqrt(red[0] / (2.0 * f.n_samples));
+    if (!(st > 0.0)) st = 1.0;
+    const float inv = (float)(1.0 / st);
+    for (int i = threadIdx.x; i < 2 * f.n_samples; i += 256) t[i] *= inv;
+    if (threadIdx.x == 0) tile_hdr(f, tile)[9] = st;
+}
+
+// ---------------------------------------------------------------- fit: training
+
+// One workgroup (4 waves) trains one tile's network with mini-batch Adam.  Each wave takes
+// 32-sample chunks; per chunk: forward, output delta, backward through layers 2 and 1, then the
+// weight gradients contract over the chunk's samples through LDS.  The four waves' gradients
+// are summed in a fixed order, then every thread updates its share of the parameters (master
+// weights and Adam moments in global memory, bfloat16 copies in LDS).
+__global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
+    __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
+    __shared__ float sbias[130];
+    __shared__ float red[kNParams];
+    __shared__ __attribute__((aligned(16))) uint16_t sz2[4][64 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t sh1[4][64 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t sz1[4][64 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t sh2[4][64 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t sphi[4][16 * 32];
+    __shared__ float sd3[4][2 * 32];
+
+    const uint32_t tile = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
+    float *state = f.state + (size_t)tile * 3 * kNParams;  // master, m, v
+    const float *tgt = f.targets + (size_t)tile * f.n_samples * 2;
+
+    for (int p = tid; p < kNParams; p += 256) {
+        const float w = f.init_params[p];
+        state[p] = w;
+        state[kNParams + p] = 0.f;
+        state[2 * kNParams + p] = 0.f;
+        const uint16_t b = to_bf16(w);
+        Wbf[p] = b;
+        if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+        if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
+        if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
+        if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
+    }
+    __syncthreads();
+
+    const int rounds = f.batch / 128;
+    double b1t = 1.0, b2t = 1.0;
+    for (int step = 1; step <= f.steps; ++step) {
+        const int i0 = (int)(((int64_t)(step - 1) * f.batch) % f.n_samples);
+        f32x16 g2[2][2] = {};
+        f32x4 g1[4] = {};
+        float gb1 = 0.f, gb2 = 0.f, gw30 = 0.f, gw31 = 0.f, gb3 = 0.f;
+        uint16_t *z2s = sz2[wave], *h1s = sh1[wave], *z1s = sz1[wave], *h2s = sh2[wave], *phs = sphi[wave];
+        float *d3s = sd3[wave];
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int si = i0 + 32 * (4 * rd + wave) + col;
+            const float u = f.samples[2 * si + hf];
+            const float t0 = tgt[2 * si], t1 = tgt[2 * si + 1];
+            uint16_t phi8[8];
+            features8(u, phi8);
+            Fwd fw;
+            forward32(Wbf, sbias, phi8, lane, fw);
+            const float inv_b = 1.0f / (float)f.batch;
+            const float d30 = (fw.o[0] - t0) * inv_b, d31 = (fw.o[1] - t1) * inv_b;
+            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3
+            uint16_t dz2[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int un = slot_unit(q, hf);
+                const float dh = fmaf(from_bf16(Wbf[kOffW3 + un]), d30, from_bf16(Wbf[kOffW3 + 64 + un]) * d31);
+                const float s = sigm(fw.z2[q]);
+                dz2[q] = to_bf16(dh * (s * (1.0f + fw.z2[q] * (1.0f - s))));
+            }
+            // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
+            uint16_t dz1[32];
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+                const int R = 32 * T + col;
+                f32x16 acc = {};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const bf16x8 a = lds8(W2T + perm_row(R) * 64 + 16 * kk + 8 * hf);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(dz2 + 8 * kk), acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const float z = fw.z1[16 * T + q];
+                    const float s = sigm(z);
+                    dz1[16 * T + q] = to_bf16(acc[q] * (s * (1.0f + z * (1.0f - s))));
+                }
+            }
+            // stage [unit][sample] copies for the weight gradients
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int un = slot_unit(q, hf);
+                z2s[un * 32 + col] = dz2[q];
+                h1s[un * 32 + col] = fw.h1[q];
+                z1s[un * 32 + col] = dz1[q];
+                h2s[un * 32 + col] = fw.h2[q];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) phs[(8 * hf + i) * 32 + col] = phi8[i];
+            if (hf == 0) {
+                d3s[col] = d30;
+                d3s[32 + col] = d31;
+            }
+            __syncthreads();
+            // dW2 += dz2^T h1 (K = 32 samples)
+#pragma unroll
+            for (int TA = 0; TA < 2; ++TA)
+#pragma unroll
+                for (int TB = 0; TB < 2; ++TB)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb) {
+                        const bf16x8 a = lds8(z2s + (32 * TA + col) * 32 + 16 * kb + 8 * hf);
+                        const bf16x8 b = lds8(h1s + (32 * TB + col) * 32 + 16 * kb + 8 * hf);
+                        g2[TA][TB] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, g2[TA][TB], 0, 0, 0);
+                    }
+            // dW1 += dz1^T phi (16x16x32: K = 32 samples)
+#pragma unroll
+            for (int T4 = 0; T4 < 4; ++T4) {
+                const bf16x8 a = lds8(z1s + (16 * T4 + (lane & 15)) * 32 + 8 * (lane >> 4));
+                const bf16x8 b = lds8(phs + (lane & 15) * 32 + 8 * (lane >> 4));
+                g1[T4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1[T4], 0, 0, 0);
+            }
+            // bias gradients and dW3: lane = hidden unit
+            {
+                float s1 = 0.f, s2 = 0.f, w0 = 0.f, w1 = 0.f;
+                for (int s = 0; s < 32; ++s) {
+                    s2 += from_bf16(z2s[lane * 32 + s]);
+                    s1 += from_bf16(z1s[lane * 32 + s]);
+                    const float h = from_bf16(h2s[lane * 32 + s]);
+                    w0 = fmaf(d3s[s], h, w0);
+                    w1 = fmaf(d3s[32 + s], h, w1);
+                }
+                gb2 += s2;
+                gb1 += s1;
+                gw30 += w0;
+                gw31 += w1;
+                if (lane < 2) {
+                    float s3 = 0.f;
+                    for (int s = 0; s < 32; ++s) s3 += d3s[32 * lane + s];
+                    gb3 += s3;
+                }
+            }
+            __syncthreads();
+        }
+        // sum the waves' gradients into red[] in wave order
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w) {
+                auto put = [&](int idx, float v) { red[idx] = (w == 0) ? v : red[idx] + v; };
+#pragma unroll
+                for (int TA = 0; TA < 2; ++TA)
+#pragma unroll
+                    for (int TB = 0; TB < 2; ++TB)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int j = 32 * TA + 8 * (r >> 2) + 4 * hf + (r & 3), i = 32 * TB + col;
+                            put(kOffW2 + j * 64 + i, g2[TA][TB][r]);
+                        }
+#pragma unroll
+                for (int T4 = 0; T4 < 4; ++T4)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) put(kOffW1 + (16 * T4 + 4 * (lane >> 4) + r) * 16 + (lane & 15), g1[T4][r]);
+                put(kOffB1 + lane, gb1);
+                put(kOffB2 + lane, gb2);
+                put(kOffW3 + lane, gw30);
+                put(kOffW3 + 64 + lane, gw31);
+                if (lane < 2) put(kOffB3 + lane, gb3);
+            }
+            __syncthreads();
+        }
+        if (f.debug_grad && step == 1)
+            for (int p = tid; p < kNParams; p += 256) f.debug_grad[(size_t)tile * kNParams + p] = red[p];
+        // Adam with bias correction and a cosine-decayed learning rate
+        b1t *= 0.9;
+        b2t *= 0.999;
+        const float lr_t = (float)((double)f.lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (step - 1) / f.steps)));
+        const float bc1 = (float)(1.0 - b1t), bc2 = (float)(1.0 - b2t);
+        for (int p = tid; p < kNParams; p += 256) {
+            const float g = red[p];
+            float w = state[p], m = state[kNParams + p], v = state[2 * kNParams + p];
+            m = 0.9f * m + 0.1f * g;
+            v = 0.999f * v + 0.001f * g * g;
+            w -= lr_t * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+            state[p] = w;
+            state[kNParams + p] = m;
+            state[2 * kNParams + p] = v;
+            const uint16_t b = to_bf16(w);
+            Wbf[p] = b;
+            if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+            if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
+            if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
+            if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
+        }
+        __syncthreads();
+    }
+    // the fitted network: bfloat16 weights and FP32 biases (biases kept at full precision)
+    uint16_t *wout = tile_w(f, tile);
+    float *bout = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(wout) + kTileBiasOff);
+    for (int p = tid; p < kNParams; p += 256) wout[p] = Wbf[p];
+    for (int p = tid; p < 130; p += 256) bout[p] = sbias[p];
+}
+
+// ---------------------------------------------------------------- eval: cell grid
+
+__device__ __forceinline__ int cell_of(const CellArgs &g, float x, float y)
+{
+    const double fx = floor(((double)x - g.ox) / g.cs), fy = floor(((double)y - g.oy) / g.cs);
+    if (!(fx >= 0.0 && fx < (double)g.ncx && fy >= 0.0 && fy < (double)g.ncy)) return -1;
+    return (int)fy * g.ncx + (int)fx;
+}
+
+__global__ void k_cells_count(const CellArgs g)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n_lens; i += stride) {
+        const float4 l = g.lenses[i];
+        const int c = cell_of(g, l.x, l.y);
+        if (c >= 0) atomicAdd(&g.count[c], 1);
+    }
+}
+
+// Exclusive scan of count[0 .. n_cells) into start[0 .. n_cells] with one workgroup.
+__global__ void __launch_bounds__(1024) k_cells_scan(const CellArgs g)
+{
+    __shared__ int part[1024];
+    const int n = g.n_cells, tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = min(n, tid * per), e = min(n, b + per);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += g.count[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int i = b; i < e; ++i) {
+        g.start[i] = run;
+        run += g.count[i];
+    }
+    if (tid == 1023) g.start[n] = part[1023];
+}
+
+__global__ void k_cells_fill(const CellArgs g)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n_lens; i += stride) {
+        const float4 l = g.lenses[i];
+        const int c = cell_of(g, l.x, l.y);
+        if (c >= 0) g.idx[g.start[c] + atomicAdd(&g.cursor[c], 1)] = (int)i;
+    }
+}
+
+// Lens indices of every cell in increasing order, so the near-field order is deterministic.
+__global__ void k_cells_sort(const CellArgs g)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n_cells) return;
+    const int b = g.start[c], e = g.start[c + 1];
+    for (int i = b + 1; i < e; ++i) {
+        const int v = g.idx[i];
+        int j = i - 1;
+        while (j >= b && g.idx[j] > v) {
+            g.idx[j + 1] = g.idx[j];
+            --j;
+        }
+        g.idx[j + 1] = v;
+    }
+}
+
+// ---------------------------------------------------------------- eval: surrogate
+
+// One workgroup per fit tile.  Rays go 128 at a time (32 per wave, a lane pair per ray): far
+// field from the affine base plus the network (layers 1-2 on MFMA), near field summed exactly
+// over the candidate lenses of the cells around the tile (far ones masked to zero-mass
+// padding), the two lanes of a ray splitting the lenses; then the FP64 lens equation and
+// wave-aggregated binning into the job's map.
+template <bool DUMP>
+__global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellArgs g)
+{
+    constexpr int CAP = 2048, T = 16;
+    __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
+    __shared__ float sbias[130];
+    __shared__ float4 s_near[CAP];
+    __shared__ int s_cells[4];
+    __shared__ uint32_t s_lost;
+
+    const uint32_t tile = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
+    double lo[2], hi[2], c[2], hw[2];
+    int64_t i0[2];
+    int n[2];
+    tile_geom(f, tile, lo, hi, c, hw, i0, n);
+    const double *hd = tile_hdr(f, tile);
+    const double a01 = hd[4], a02 = hd[5], j11 = hd[6], j12 = hd[7], j22 = hd[8], st = hd[9];
+    const uint16_t *wsrc = tile_w(f, tile);
+    const float *bsrc = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(wsrc) + kTileBiasOff);
+    for (int p = tid; p < kNParams; p += 256) Wbf[p] = wsrc[p];
+    for (int p = tid; p < 130; p += 256) sbias[p] = bsrc[p];
+    if (tid == 0) {
+        s_lost = 0u;
+        // candidate cells: those overlapping the tile rectangle grown by r_near
+        s_cells[0] = max(0, (int)floor((lo[0] - f.r_near - g.ox) / g.cs));
+        s_cells[1] = min(g.ncx - 1, (int)floor((hi[0] + f.r_near - g.ox) / g.cs));
+        s_cells[2] = max(0, (int)floor((lo[1] - f.r_near - g.oy) / g.cs));
+        s_cells[3] = min(g.ncy - 1, (int)floor((hi[1] + f.r_near - g.oy) / g.cs));
+    }
+    __syncthreads();
+    const int cx0 = s_cells[0], cx1 = s_cells[1], cy0 = s_cells[2], cy1 = s_cells[3];
+    const int ncx = max(0, cx1 - cx0 + 1);
+    const int n_rows = max(0, cy1 - cy0 + 1);
+    // candidate lenses are the concatenation of cell rows cy0..cy1, each the contiguous index
+    // range start[cy * ncx_grid + cx0] .. start[cy * ncx_grid + cx1 + 1]
+    int n_cand = 0;
+    for (int r = 0; r < n_rows; ++r) {
+        const int row = (cy0 + r) * g.ncx;
+        n_cand += g.start[row + cx1 + 1] - g.start[row + cx0];
+    }
+    const double rn2 = f.r_near * f.r_near;
+    const int n_batches = (n_cand + CAP - 1) / CAP;
+
+    // stage candidates [b CAP, b CAP + CAP) (far ones become zero-mass padding)
+    auto stage = [&](int b) {
+        const int base = b * CAP;
+        for (int k = tid; k < CAP; k += 256) {
+            float4 v = make_float4(kPadCoord, kPadCoord, 0.f, 0.f);
+            int e = base + k;
+            if (e < n_cand) {
+                for (int r = 0; r < n_rows; ++r) {
+                    const int row = (cy0 + r) * g.ncx;
+                    const int len = g.start[row + cx1 + 1] - g.start[row + cx0];
+                    if (e < len) {
+                        const float4 l = g.lenses[g.idx[g.start[row + cx0] + e]];
+                        if (is_near(l.x, l.y, lo, hi, rn2)) v = l;
+                        break;
+                    }
+                    e -= len;
+                }
+            }
+            s_near[k] = v;
+        }
+    };
+    if (n_batches == 1) stage(0);
+    __syncthreads();
+
+    const int n_rays = n[0] * n[1];
+    const int passes = (f.TX * f.TY + 127) / 128;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int ri = 128 * ps + 32 * wave + col;
+        const int ix = ri % f.TX, iy = ri / f.TX;
+        const bool active = ri < f.TX * f.TY && ix < n[0] && iy < n[1];
+        const float x1 = ray_coord(f.glo1, f.gt1, i0[0] + ix);
+        const float x2 = ray_coord(f.glo2, f.gt2, i0[1] + iy);
+        // far field: network
+        float o0 = 0.f, o1 = 0.f;
+        if (!f.affine_only) {
+            const float u = hf == 0 ? (float)(((double)x1 - c[0]) / hw[0]) : (float)(((double)x2 - c[1]) / hw[1]);
+            uint16_t phi8[8];
+            features8(u, phi8);
+            Fwd fw;
+            forward32(Wbf, sbias, phi8, lane, fw);
+            o0 = fw.o[0];
+            o1 = fw.o[1];
+        }
+        // near field: this lane takes half hf of every staged batch
+        double A1 = 0.0, A2 = 0.0;
+        for (int b = 0; b < n_batches; ++b) {
+            if (n_batches > 1) {
+                __syncthreads();
+                stage(b);
+                __syncthreads();
+            }
+            // the two lanes of a ray split the batch: [0, half) and [half, nb), in runs of T
+            const int nb = min(CAP, n_cand - b * CAP);
+            const int half = ((nb + 1) / 2 + T - 1) / T * T;
+            const float4 *L = s_near + (hf ? half : 0);
+            const int m = hf ? max(0, nb - half) : min(half, nb);
+            const int mr = (m + T - 1) / T * T;
+            for (int r = 0; r < mr; r += T) {
+                float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+                for (int j = 0; j < T; ++j) {
+                    const float4 l = L[r + j];
+                    const float dx = x1 - l.x, dy = x2 - l.y;
+                    const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                    s1 = fmaf(d, dx, s1);
+                    s2 = fmaf(d, dy, s2);
+                }
+                A1 += (double)s1;
+                A2 += (double)s2;
+            }
+        }
+        const double B1 = __shfl_xor(A1, 32), B2 = __shfl_xor(A2, 32);
+        const double N1 = (hf == 0 ? A1 + B1 : B1 + A1) * kRcpBiasComp;
+        const double N2 = (hf == 0 ? A2 + B2 : B2 + A2) * kRcpBiasComp;
+        const double d1 = (double)x1 - c[0], d2 = (double)x2 - c[1];
+        const double F1 = a01 + j11 * d1 + j12 * d2 + st * (double)o0;
+        const double F2 = a02 + j12 * d1 + j22 * d2 + st * (double)o1;
+        const double y1 = f.lam1 * (double)x1 - (F1 + N1);
+        const double y2 = f.lam2 * (double)x2 - (F2 + N2);
+        int key = -2;
+        if (active && hf == 0) {
+            const double p1 = floor((y1 - f.mlo1) * f.ms1), p2 = floor((y2 - f.mlo2) * f.ms2);
+            key = (p1 >= 0.0 && p1 < (double)f.mn1 && p2 >= 0.0 && p2 < (double)f.mn2) ? (int)p2 * f.mn1 + (int)p1 : -1;
+            if (DUMP) {
+                const int64_t rw = (i0[1] + iy - f.wlo2) * f.wn1 + (i0[0] + ix - f.wlo1);
+                f.ray_y[2 * rw] = y1;
+                f.ray_y[2 * rw + 1] = y2;
+                f.ray_pix[rw] = key;
+            }
+        }
+        // runs of equal keys over consecutive lanes are added once
+        const int prev = __shfl_up(key, 1);
+        const bool head = (lane == 0) || (key != prev);
+        const unsigned long long H = __ballot(head);
+        const unsigned long long above = lane == 63 ? 0ull : (H >> (lane + 1));
+        const int nxt = above ? lane + 1 + __builtin_ctzll(above) : 64;
+        if (head && key >= 0) atomicAdd(&f.counts[key], (uint32_t)(nxt - lane));
+        if (head && key == -1) atomicAdd(&s_lost, (uint32_t)(nxt - lane));
+    }
+    (void)n_rays;
+    __syncthreads();
+    if (tid == 0 && s_lost) atomicAdd(f.lost, (unsigned long long)s_lost);
+}
+
+__global__ void k_write_model_header(uint8_t *model, uint64_t hash, int64_t n_tiles, int tiles_x, int tiles_y, int TX,
+                                     int TY)
+{
+    uint64_t *h = reinterpret_cast<uint64_t *>(model);
+    h[0] = kModelMagic;
+    h[1] = hash;
+    h[2] = (uint64_t)n_tiles;
+    int32_t *d = reinterpret_cast<int32_t *>(model + 24);
+    d[0] = tiles_x;
+    d[1] = tiles_y;
+    d[2] = TX;
+    d[3] = TY;
+}
+
+}  // namespace
+
+hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
+{
+    const uint32_t nt = (uint32_t)f.n_tiles;
+    hipLaunchKernelGGL(k_write_model_header, dim3(1), dim3(1), 0, s, f.model, hash, f.n_tiles, f.tiles_x, f.tiles_y,
+                       f.TX, f.TY);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ff_affine, dim3(nt), dim3(256), 0, s, f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ff_samples, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_train, dim3(nt), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
+{
+    hipError_t e;
+    const int cb = (int)std::min<int64_t>(4096, (g.n_lens + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_cells_count, dim3(cb), dim3(256), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cells_scan, dim3(1), dim3(1024), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cells_fill, dim3(cb), dim3(256), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cells_sort, dim3((g.n_cells + 255) / 256), dim3(256), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (f.ray_y)
+        hipLaunchKernelGGL((k_surrogate<true>), dim3((uint32_t)f.n_tiles), dim3(256), 0, s, f, g);
+    else
+        hipLaunchKernelGGL((k_surrogate<false>), dim3((uint32_t)f.n_tiles), dim3(256), 0, s, f, g);
+    return hipGetLastError();
+}
+
+}  // namespace rs

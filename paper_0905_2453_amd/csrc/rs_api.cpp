@@ -365,6 +365,126 @@ std::string tune_key(const rs_job *jobs, int32_t n_jobs)
     return o.str();
 }
 
+// ---------------------------------------------------------------- learned far field
+
+struct FarGeom {
+    int64_t tiles_x, tiles_y, n_tiles;
+    int32_t TX, TY;
+    double cs;
+};
+
+int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g)
+{
+    int st = validate_job(job);
+    if (st != RS_OK) return st;
+    if (!c) return fail(RS_EINVAL, "far-field config is NULL");
+    if (c->tile_rays[0] <= 0 || c->tile_rays[1] <= 0) return fail(RS_EINVAL, "tile_rays must be > 0");
+    if (!(c->r_near > 0.0) || !std::isfinite(c->r_near)) return fail(RS_EINVAL, "r_near must be finite and > 0");
+    if (c->n_samples <= 0 || c->n_samples % 1024) return fail(RS_EINVAL, "n_samples must be a positive multiple of 1024");
+    if (c->steps < 0) return fail(RS_EINVAL, "steps < 0");
+    if (c->batch <= 0 || c->batch % 128 || c->n_samples % c->batch)
+        return fail(RS_EINVAL, "batch must be a multiple of 128 dividing n_samples");
+    if (!(c->lr >= 0.0f) || !std::isfinite(c->lr)) return fail(RS_EINVAL, "lr must be finite and >= 0");
+    if (!(c->cell_size >= 0.0) || !std::isfinite(c->cell_size)) return fail(RS_EINVAL, "cell_size must be >= 0");
+    g.TX = c->tile_rays[0];
+    g.TY = c->tile_rays[1];
+    g.tiles_x = (job->grid.win_n[0] + g.TX - 1) / g.TX;
+    g.tiles_y = (job->grid.win_n[1] + g.TY - 1) / g.TY;
+    g.n_tiles = g.tiles_x * g.tiles_y;
+    if (g.n_tiles >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many far-field tiles");
+    g.cs = c->cell_size > 0.0 ? c->cell_size : c->r_near / 4.0;
+    return RS_OK;
+}
+
+uint64_t ff_hash(const rs_job *job, const rs_ff_config *c)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    mix(&job->grid, sizeof job->grid);
+    mix(&job->n_lens, sizeof job->n_lens);
+    mix(c->tile_rays, sizeof c->tile_rays);
+    mix(&c->r_near, sizeof c->r_near);
+    mix(&c->n_samples, sizeof c->n_samples);
+    mix(&c->steps, sizeof c->steps);
+    mix(&c->batch, sizeof c->batch);
+    mix(&c->lr, sizeof c->lr);
+    return h;
+}
+
+rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
+{
+    const rs_raygrid &gr = job->grid;
+    rs::FarArgs f{};
+    f.lenses = reinterpret_cast<const float4 *>(job->lenses);
+    f.n_lens = job->n_lens;
+    f.glo1 = gr.lo[0];
+    f.glo2 = gr.lo[1];
+    f.gt1 = (gr.hi[0] - gr.lo[0]) / (double)gr.n[0];
+    f.gt2 = (gr.hi[1] - gr.lo[1]) / (double)gr.n[1];
+    f.wlo1 = gr.win_lo[0];
+    f.wlo2 = gr.win_lo[1];
+    f.wn1 = gr.win_n[0];
+    f.wn2 = gr.win_n[1];
+    f.TX = g.TX;
+    f.TY = g.TY;
+    f.tiles_x = (int32_t)g.tiles_x;
+    f.tiles_y = (int32_t)g.tiles_y;
+    f.n_tiles = g.n_tiles;
+    f.r_near = c->r_near;
+    f.samples = c->samples;
+    f.init_params = c->init_params;
+    f.n_samples = c->n_samples;
+    f.parts = c->n_samples / 1024;
+    f.steps = c->steps;
+    f.batch = c->batch;
+    f.lr = c->lr;
+    f.debug_grad = c->debug_grad;
+    f.debug_targets = c->debug_targets;
+    f.lam1 = (1.0 - job->macro.gamma) - job->macro.kappa_c;
+    f.lam2 = (1.0 + job->macro.gamma) - job->macro.kappa_c;
+    f.mlo1 = job->map.lo[0];
+    f.mlo2 = job->map.lo[1];
+    f.ms1 = (double)job->map.n[0] / (job->map.hi[0] - job->map.lo[0]);
+    f.ms2 = (double)job->map.n[1] / (job->map.hi[1] - job->map.lo[1]);
+    f.mn1 = job->map.n[0];
+    f.mn2 = job->map.n[1];
+    f.counts = job->counts;
+    f.lost = reinterpret_cast<unsigned long long *>(job->n_lost);
+    return f;
+}
+
+size_t fit_ws_bytes(const FarGeom &g, const rs_ff_config *c)
+{
+    return align256((size_t)g.n_tiles * c->n_samples * 2 * sizeof(float)) +
+           align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)) + 256;
+}
+
+// Cell grid around the ray window grown by r_near (plus one cell): only lenses there can be near.
+void cell_geom(const rs_job *job, const rs_ff_config *c, const FarGeom &g, double &ox, double &oy, int64_t &ncx,
+               int64_t &ncy)
+{
+    const rs_raygrid &gr = job->grid;
+    const double t1 = (gr.hi[0] - gr.lo[0]) / (double)gr.n[0], t2 = (gr.hi[1] - gr.lo[1]) / (double)gr.n[1];
+    const double x0 = gr.lo[0] + (double)gr.win_lo[0] * t1, x1 = gr.lo[0] + (double)(gr.win_lo[0] + gr.win_n[0]) * t1;
+    const double y0 = gr.lo[1] + (double)gr.win_lo[1] * t2, y1 = gr.lo[1] + (double)(gr.win_lo[1] + gr.win_n[1]) * t2;
+    ox = x0 - c->r_near - g.cs;
+    oy = y0 - c->r_near - g.cs;
+    ncx = (int64_t)std::ceil((x1 + c->r_near + g.cs - ox) / g.cs);
+    ncy = (int64_t)std::ceil((y1 + c->r_near + g.cs - oy) / g.cs);
+}
+
+size_t eval_ws_bytes(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
+{
+    double ox, oy;
+    int64_t ncx, ncy;
+    cell_geom(job, c, g, ox, oy, ncx, ncy);
+    const size_t cells = (size_t)(ncx * ncy);
+    return align256(cells * 4) * 2 + align256((cells + 1) * 4) + align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4) + 256;
+}
+
 }  // namespace
 
 extern "C" {
@@ -536,6 +656,108 @@ int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, siz
         if (out) out << key << ' ' << win.K1 << ' ' << win.K2 << ' ' << win.LT << ' ' << win.W << '\n';
     }
     return RS_OK;
+}
+
+size_t rs_farfield_model_bytes(const rs_job *job, const rs_ff_config *cfg)
+{
+    FarGeom g;
+    if (validate_ff(job, cfg, g) != RS_OK) return 0;
+    return rs::kModelHeader + (size_t)g.n_tiles * rs::kTileRecord;
+}
+
+size_t rs_farfield_fit_workspace_bytes(const rs_job *job, const rs_ff_config *cfg)
+{
+    FarGeom g;
+    if (validate_ff(job, cfg, g) != RS_OK) return 0;
+    return fit_ws_bytes(g, cfg);
+}
+
+size_t rs_farfield_eval_workspace_bytes(const rs_job *job, const rs_ff_config *cfg)
+{
+    FarGeom g;
+    if (validate_ff(job, cfg, g) != RS_OK) return 0;
+    double ox, oy;
+    int64_t ncx, ncy;
+    cell_geom(job, cfg, g, ox, oy, ncx, ncy);
+    if (ncx * ncy >= (int64_t(1) << 31)) return 0;
+    return eval_ws_bytes(job, cfg, g);
+}
+
+int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, size_t model_bytes, void *workspace,
+                    size_t ws_bytes, void *stream)
+{
+    g_err[0] = '\0';
+    FarGeom g;
+    int st = validate_ff(job, cfg, g);
+    if (st != RS_OK) return st;
+    if (!cfg->samples || !cfg->init_params) return fail(RS_EINVAL, "samples and init_params are required");
+    if (!model || !workspace) return fail(RS_EINVAL, "model and workspace are required");
+    const size_t need_m = rs::kModelHeader + (size_t)g.n_tiles * rs::kTileRecord;
+    if (model_bytes < need_m) return fail(RS_ESMALLBUF, "model %zu bytes < %zu needed", model_bytes, need_m);
+    const size_t need_w = fit_ws_bytes(g, cfg);
+    if (ws_bytes < need_w) return fail(RS_ESMALLBUF, "workspace %zu bytes < %zu needed", ws_bytes, need_w);
+    if ((uintptr_t)model & 255) return fail(RS_EINVAL, "model must be 256-byte aligned");
+    if (g.n_tiles == 0) return RS_OK;
+    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    rs::FarArgs f = far_args(job, cfg, g);
+    f.model = static_cast<uint8_t *>(model);
+    f.targets = reinterpret_cast<float *>(base);
+    f.state = reinterpret_cast<float *>(base + align256((size_t)g.n_tiles * cfg->n_samples * 2 * sizeof(float)));
+    const hipError_t e = rs::launch_ff_fit(f, ff_hash(job, cfg), reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RS_OK : dev_fail(e, "far-field fit launch");
+}
+
+int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
+                     void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts)
+{
+    g_err[0] = '\0';
+    FarGeom g;
+    int st = validate_ff(job, cfg, g);
+    if (st != RS_OK) return st;
+    if (!model || !workspace) return fail(RS_EINVAL, "model and workspace are required");
+    if (opts && ((opts->ray_y == nullptr) != (opts->ray_pix == nullptr)))
+        return fail(RS_EINVAL, "ray_y and ray_pix must be given together");
+    const size_t need_m = rs::kModelHeader + (size_t)g.n_tiles * rs::kTileRecord;
+    if (model_bytes < need_m) return fail(RS_ESMALLBUF, "model %zu bytes < %zu needed", model_bytes, need_m);
+    double ox, oy;
+    int64_t ncx, ncy;
+    cell_geom(job, cfg, g, ox, oy, ncx, ncy);
+    if (ncx * ncy >= (int64_t(1) << 31)) return fail(RS_ERANGE, "cell grid too large; raise cell_size");
+    const size_t need_w = eval_ws_bytes(job, cfg, g);
+    if (ws_bytes < need_w) return fail(RS_ESMALLBUF, "workspace %zu bytes < %zu needed", ws_bytes, need_w);
+    if (opts && (opts->flags & RS_FLAG_FAULT_INJECT)) return fail(RS_EDEVICE, "injected fault (RS_FLAG_FAULT_INJECT)");
+    if (g.n_tiles == 0) return RS_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the model must have been fitted for this grid, tiling and configuration
+    uint64_t hdr[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(hdr, model, sizeof hdr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(e, "model header read");
+    if (hdr[0] != rs::kModelMagic || hdr[1] != ff_hash(job, cfg))
+        return fail(RS_ENOTFIT, "model was not fitted for this job and configuration");
+    rs::FarArgs f = far_args(job, cfg, g);
+    f.model = const_cast<uint8_t *>(static_cast<const uint8_t *>(model));
+    f.ray_y = opts ? opts->ray_y : nullptr;
+    f.ray_pix = opts ? opts->ray_pix : nullptr;
+    f.affine_only = (opts && (opts->flags & RS_FLAG_AFFINE_ONLY)) ? 1 : 0;
+    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    const size_t cells = (size_t)(ncx * ncy);
+    rs::CellArgs cg{};
+    cg.lenses = f.lenses;
+    cg.n_lens = job->n_lens;
+    cg.ox = ox;
+    cg.oy = oy;
+    cg.cs = g.cs;
+    cg.ncx = (int32_t)ncx;
+    cg.ncy = (int32_t)ncy;
+    cg.n_cells = (int32_t)cells;
+    cg.count = reinterpret_cast<int32_t *>(base);
+    cg.cursor = reinterpret_cast<int32_t *>(base + align256(cells * 4));
+    cg.start = reinterpret_cast<int32_t *>(base + 2 * align256(cells * 4));
+    cg.idx = reinterpret_cast<int32_t *>(base + 2 * align256(cells * 4) + align256((cells + 1) * 4));
+    e = rs::launch_zero(reinterpret_cast<uint32_t *>(base), (int64_t)(2 * align256(cells * 4) / 4), s);
+    if (e == hipSuccess) e = rs::launch_ff_eval(f, cg, s);
+    return e == hipSuccess ? RS_OK : dev_fail(e, "far-field eval launch");
 }
 
 void rs_release_graphs(void)

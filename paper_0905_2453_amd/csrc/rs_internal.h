@@ -45,6 +45,63 @@ struct BatchArgs {
     uint32_t *queue;            // work-item counter, zeroed before each launch
 };
 
+// ---------------------------------------------------------------- learned far field
+
+// Network parameter layout (flat, logical order): W1 [64][16], b1 [64], W2 [64][64], b2 [64],
+// W3 [2][64], b3 [2].
+constexpr int kNParams = 5378;
+constexpr int kNParamsPad = 5384;
+constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248, kOffB3 = 5376;
+// Model buffer: 256-byte header, then one record per tile: 10 doubles (c1, c2, h1, h2,
+// alpha_far(c) 1 and 2, J11, J12, J22, s_t) padded to 128 bytes, the bfloat16 parameters
+// (5378 x 2 bytes, padded to 16) and the 130 FP32 biases (b1, b2, b3).
+constexpr size_t kModelHeader = 256;
+constexpr size_t kTileWeightsOff = 128;
+constexpr size_t kTileBiasOff = ((size_t)kNParams * 2 + 15) / 16 * 16;
+constexpr size_t kTileRecord = (kTileWeightsOff + kTileBiasOff + 130 * 4 + 255) / 256 * 256;
+constexpr uint64_t kModelMagic = 0x3130304646535252ull;  // "RRSFF001"
+
+struct FarArgs {
+    const float4 *lenses;
+    int64_t n_lens;
+    double glo1, glo2, gt1, gt2;  // grid lower corner and cell size
+    int64_t wlo1, wlo2, wn1, wn2; // ray window
+    int32_t TX, TY;               // rays per tile along each axis
+    int32_t tiles_x, tiles_y;
+    int64_t n_tiles;
+    double r_near;
+    // fit
+    const float *samples;         // n_samples x 2 tile-local points in [-1, 1]^2
+    const float *init_params;     // kNParams
+    float *targets;               // n_tiles x n_samples x 2 (workspace)
+    float *state;                 // n_tiles x 3 x kNParams (workspace: master, m, v)
+    int32_t n_samples, parts, steps, batch;
+    float lr;
+    float *debug_grad;            // optional n_tiles x kNParams: gradient of the first step
+    float *debug_targets;         // optional n_tiles x n_samples x 2: unnormalised residuals
+    uint8_t *model;
+    // eval
+    double lam1, lam2, mlo1, mlo2, ms1, ms2;
+    int32_t mn1, mn2;
+    uint32_t *counts;
+    unsigned long long *lost;
+    double *ray_y;
+    int32_t *ray_pix;
+    int32_t affine_only;
+};
+
+// Uniform grid of lens cells around the ray window (near-field candidates).
+struct CellArgs {
+    const float4 *lenses;
+    int64_t n_lens;
+    double ox, oy, cs;
+    int32_t ncx, ncy, n_cells;
+    int32_t *count, *cursor, *start, *idx;  // n_cells, n_cells, n_cells + 1, n_lens
+};
+
+hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s);
+hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
+
 // Per-lane ray blocks (K1 columns x K2 rows) compiled into the library.
 bool ray_block_supported(int K1, int K2);
 // Launch the direct-sum kernel for a K1 x K2 ray block per lane, T-lens float32 runs and LT-lens

@@ -277,3 +277,24 @@ def sample_indices(seed: int, total: int, count: int, stream: int = STREAM_PROBE
     sel = hash_u64(seed + 1, stream, np.arange(len(got), dtype=np.uint64))
     order = np.argsort(sel, kind="stable")[:count]
     return np.sort(got[order])
+
+
+# --------------------------------------------------------------------------
+# inputs of the learned far-field fit
+# --------------------------------------------------------------------------
+
+def fit_samples(seed: int, n: int = 4096) -> np.ndarray:
+    """n tile-local sample points uniform in [-1, 1]^2 (float32, n x 2)."""
+    return (uniform(seed, STREAM_SAMPLES, 0, 2 * n).reshape(n, 2) * 2.0 - 1.0).astype(np.float32)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Glorot-uniform initial parameters of the 16 -> 64 -> 64 -> 2 network, zero biases
+    (float32, 5378 values in the order W1 [64][16], b1, W2 [64][64], b2, W3 [2][64], b3)."""
+    p = np.zeros(5378, dtype=np.float64)
+    u = uniform(seed, STREAM_INIT, 0, 5378)
+    for off, fan_in, fan_out in ((0, 16, 64), (1088, 64, 64), (5248, 64, 2)):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        n = fan_in * fan_out
+        p[off:off + n] = (2.0 * u[off:off + n] - 1.0) * a
+    return p.astype(np.float32)

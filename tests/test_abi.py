@@ -185,3 +185,46 @@ def test_batched_validation_without_device():
     o.flags = _abi.RS_FLAG_FAULT_INJECT
     assert L.rs_shoot_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need, None, ctypes.byref(o)) == -3
     assert L.rs_autotune_batched(arr_ok, 2, ctypes.c_void_p(0x4000), need, None, None, None) == -1
+
+
+def _ffcfg(**kw):
+    from paper_0905_2453_amd import _abi
+    c = _abi.FFConfig()
+    c.tile_rays[0], c.tile_rays[1] = 16, 16
+    c.r_near, c.n_samples, c.steps, c.batch, c.lr = 8.0, 1024, 10, 512, 1e-2
+    c.samples, c.init_params = 0x7000, 0x8000
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_farfield_validation_without_device():
+    P, L = _lib()
+    j = _job()
+    good = _ffcfg()
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(good)) > 256
+    assert L.rs_farfield_fit_workspace_bytes(ctypes.byref(j), ctypes.byref(good)) > 0
+    assert L.rs_farfield_eval_workspace_bytes(ctypes.byref(j), ctypes.byref(good)) > 0
+    for bad in [dict(n_samples=1000), dict(batch=100), dict(batch=384), dict(steps=-1), dict(r_near=0.0),
+                dict(r_near=float("nan")), dict(lr=float("inf")), dict(cell_size=-1.0)]:
+        c = _ffcfg(**bad)
+        assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0, bad
+        st = L.rs_farfield_fit(ctypes.byref(j), ctypes.byref(c), ctypes.c_void_p(0x9000), 1 << 30,
+                               ctypes.c_void_p(0xa000), 1 << 30, None)
+        assert st == -1, bad
+    c = _ffcfg(tile_rays=(ctypes.c_int32 * 2)(0, 16))
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0
+    need = L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(good))
+    st = L.rs_farfield_fit(ctypes.byref(j), ctypes.byref(good), ctypes.c_void_p(0x9000), need - 1,
+                           ctypes.c_void_p(0xa000), 1 << 30, None)
+    assert st == -4
+    st = L.rs_farfield_fit(ctypes.byref(j), ctypes.byref(_ffcfg(samples=None)), ctypes.c_void_p(0x9000), need,
+                           ctypes.c_void_p(0xa000), 1 << 30, None)
+    assert st == -1
+    from paper_0905_2453_amd import _abi
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    ew = L.rs_farfield_eval_workspace_bytes(ctypes.byref(j), ctypes.byref(good))
+    st = L.rs_farfield_eval(ctypes.byref(j), ctypes.byref(good), ctypes.c_void_p(0x9000), need,
+                            ctypes.c_void_p(0xa000), ew, None, ctypes.byref(o))
+    assert st == -3

@@ -35,13 +35,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paper", choices=["paper", "small", "batched"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "small", "batched", "farfield", "large"])
+    ap.add_argument("--ff-steps", type=int, default=2000, help="surrogate workloads: Adam steps per tile")
     ap.add_argument("--autotune-cache", default="", help="batched workload: autotuner cache file")
     ap.add_argument("--block", default="", help="rays per lane as COLSxROWS, e.g. 2x4 (default: library's)")
     ap.add_argument("--lens-tile", type=int, default=0)
     ap.add_argument("--fp32-run", type=int, default=0)
     ap.add_argument("--map-window", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="default workload: skip the batched and learned far-field measurements")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (HBM counter calibration)")
@@ -108,7 +111,7 @@ def cpu_baseline(w, target_cpu_s: float):
                       f"FP64 single-threaded oracle on {threads} threads, {dt:.1f} s wall"}
 
 
-def bench_batched(args):
+def bench_batched(args, emit=True):
     """64 maps in one persistent, graph-replayed launch vs 64 separate rs_shoot launches."""
     import torch
     import paper_0905_2453_amd as P
@@ -184,7 +187,126 @@ def bench_batched(args):
                      "frac": FLOP_PER_INTERACTION * inter / (batched_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
                      "traffic": None, "kernel": "k_batched"},
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_surrogate(args, which=None, emit=True):
+    """Learned far-field closure vs the plain direct sum on the same rays.
+
+    farfield: 1e6 lenses, 8192^2 rays in 64x64-ray tiles; the plain sum judges the whole map.
+    large:    1e7 lenses, 32768^2 rays in 512x512-ray tiles; the closure shoots the whole grid,
+              the plain sum judges a seeded 1% of the tiles (both paths shoot those tiles).
+    """
+    import torch
+    import paper_0905_2453_amd as P
+    import synth
+    dev = torch.device("cuda:0")
+    large = (which or args.workload) == "large"
+    w = synth.workload_large() if large else synth.workload_farfield()
+    tile = (512, 512) if large else (64, 64)
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                     counts, lost)
+    samples = torch.from_numpy(synth.fit_samples(7, 4096)).to(dev)
+    init = torch.from_numpy(synth.init_params(7)).to(dev)
+    cfg = P.ff_config(samples, init, tile_rays=tile, r_near=8.0, steps=args.ff_steps, batch=512, lr=1e-2)
+    model = torch.empty(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    fws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    ews = torch.empty(P.farfield_eval_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    fit_s = timed(lambda: P.farfield_fit(job, cfg, model, fws))
+    ntx = (w.grid_n[0] + tile[0] - 1) // tile[0]
+    nty = (w.grid_n[1] + tile[1] - 1) // tile[1]
+    n_tiles = ntx * nty
+    if large:
+        judge = np.sort(synth.sample_indices(11, n_tiles, max(1, n_tiles // 100))).astype(np.int32)
+    else:
+        judge = np.arange(n_tiles, dtype=np.int32)
+    judge_t = torch.from_numpy(judge).to(dev)
+    # surrogate over the whole grid (warm once, then timed)
+    P.farfield_eval(job, cfg, model, ews)
+    counts.zero_()
+    lost.zero_()
+    eval_s = timed(lambda: P.farfield_eval(job, cfg, model, ews))
+    if int(counts.sum().item()) + int(lost.item()) != w.n_rays:
+        print("bench.py: surrogate ray conservation failed", file=sys.stderr)
+        sys.exit(3)
+    # the judged tiles: surrogate, affine-only ablation, plain direct sum
+    sub_cfg = P.ff_config(samples, init, tile_rays=tile, r_near=8.0, steps=args.ff_steps, batch=512, lr=1e-2,
+                          eval_tiles=judge_t)
+
+    def surrogate_map(flags):
+        counts.zero_()
+        lost.zero_()
+        o = P.Opts()
+        o.flags = flags
+        P.farfield_eval(job, sub_cfg if large else cfg, model, ews, o)
+        torch.cuda.synchronize()
+        return counts.cpu().numpy().view(np.uint32).astype(np.int64)
+
+    m_sur = surrogate_map(0)
+    m_aff = surrogate_map(P._abi.RS_FLAG_AFFINE_ONLY)
+    counts.zero_()
+    lost.zero_()
+    pws = torch.empty(P.workspace_bytes(job), dtype=torch.uint8, device=dev)
+    judge_rays = 0
+    plain_jobs = []
+    for t in judge:
+        tx, ty = int(t) % ntx, int(t) // ntx
+        a = (tx * tile[0], ty * tile[1])
+        n = (min(tile[0], w.grid_n[0] - a[0]), min(tile[1], w.grid_n[1] - a[1]))
+        judge_rays += n[0] * n[1]
+        plain_jobs.append(P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo,
+                                     w.map_hi, w.map_n, counts, lost, window=(a, n)))
+
+    bws = torch.empty(P.batched_workspace_bytes(plain_jobs), dtype=torch.uint8, device=dev) if large else None
+
+    def plain():
+        if large:   # the judged tiles as one persistent batched launch (full occupancy)
+            P.shoot_batched(plain_jobs, bws, None, stream)
+        else:
+            P.shoot_job(job, pws, None, stream)
+
+    plain_s = timed(plain)
+    m_pl = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+    l1 = float(np.abs(m_sur - m_pl).sum() / max(1, m_pl.sum()))
+    l1_aff = float(np.abs(m_aff - m_pl).sum() / max(1, m_pl.sum()))
+    plain_rays_s = judge_rays / plain_s
+    sur_rays_s = w.n_rays / eval_s
+    e2e_rays_s = w.n_rays / (fit_s + eval_s)
+    out = {
+        "metric": METRIC, "value": sur_rays_s, "unit": "rays/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * (fit_s + eval_s), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": w.name, "n_lens": w.n_lens, "ray_grid": list(w.grid_n), "map": list(w.map_n),
+                   "tile_rays": list(tile), "r_near": 8.0, "fit_samples": 4096, "adam_steps": args.ff_steps,
+                   "judged_tiles": int(len(judge)), "n_tiles": int(n_tiles), "parallelism": "1 GPU"},
+        "fit_s": fit_s, "eval_s": eval_s, "plain_s_on_judged_tiles": plain_s,
+        "rays_per_s": {"surrogate_eval": sur_rays_s, "surrogate_end_to_end": e2e_rays_s, "plain": plain_rays_s},
+        "speedup_vs_plain": {"eval_only": sur_rays_s / plain_rays_s, "end_to_end": e2e_rays_s / plain_rays_s},
+        "map_l1_rel_err": {"surrogate": l1, "affine_only": l1_aff, "tolerance": 0.01},
+    }
+    if l1 > 0.01:
+        print(f"bench.py: surrogate map error {l1:.3e} above the 1% tolerance", file=sys.stderr)
+        sys.exit(3)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -204,6 +326,9 @@ def main():
         sys.exit(1)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload in ("farfield", "large"):
+        bench_surrogate(args)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -275,7 +400,18 @@ def main():
                      "kernel_ms": kernel_s * 1e3,
                      "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},
     }
+    if args.workload == "paper" and not args.plain_only:
+        print("bench.py: plain direct sum done; batched maps next", file=sys.stderr, flush=True)
+        b = bench_batched(argparse.Namespace(**{**vars(args), "steps": 2, "warmup": 1}), emit=False)
+        out["batched"] = {k: b[k] for k in ("value", "batched_ms", "separate_launches_ms", "speedup_vs_separate",
+                                            "autotuned", "config")}
+        for which in ("farfield", "large"):
+            print(f"bench.py: learned far field ({which}) next", file=sys.stderr, flush=True)
+            r = bench_surrogate(args, which=which, emit=False)
+            out[f"surrogate_{which}"] = {k: r[k] for k in ("config", "fit_s", "eval_s", "plain_s_on_judged_tiles",
+                                                            "rays_per_s", "speedup_vs_plain", "map_l1_rel_err")}
     if not args.no_cpu_baseline:
+        print("bench.py: CPU oracle baseline next", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

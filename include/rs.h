@@ -205,6 +205,8 @@ typedef struct {
     const float *init_params;   /* device, 5378 initial parameters, the same for every tile (input) */
     float *debug_grad;          /* device, nullable: n_tiles x 5378, gradient of the first step      */
     float *debug_targets;       /* device, nullable: n_tiles x n_samples x 2 residual samples        */
+    const int32_t *eval_tiles;  /* device, nullable: rs_farfield_eval shoots only these tile indices  */
+    int32_t n_eval_tiles;       /* entries of eval_tiles (each in [0, n_tiles), distinct)             */
 } rs_ff_config;
 
 /*
@@ -229,8 +231,10 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
 /*
  * Shoot the job's ray window with the fitted closure and add the counts to job->counts and
  * job->n_lost (same pixel rules as rs_shoot).  opts: ray_y / ray_pix dumps and
- * RS_FLAG_AFFINE_ONLY (network off: the method without the learned part).  Reads the model
- * header first (synchronises the stream) and returns RS_ENOTFIT on a mismatch.
+ * RS_FLAG_AFFINE_ONLY (network off: the method without the learned part).  With
+ * cfg->eval_tiles only the listed tiles are shot (e.g. a seeded subset judged against
+ * rs_shoot on the same tile windows).  Reads the model header and the tile list first
+ * (synchronises the stream); RS_ENOTFIT on a model mismatch, RS_EINVAL on a bad tile index.
  */
 int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
                      void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);

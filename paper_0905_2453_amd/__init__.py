@@ -183,7 +183,7 @@ FFConfig = _abi.FFConfig
 
 
 def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, batch=512, lr=1e-2,
-              cell_size=0.0, debug_grad=None, debug_targets=None) -> FFConfig:
+              cell_size=0.0, debug_grad=None, debug_targets=None, eval_tiles=None) -> FFConfig:
     """rs_ff_config from device tensors: samples (n x 2 float32 in [-1,1]^2), init_params (5378 float32)."""
     torch = _torch()
     _require_cuda(samples, "samples", torch.float32)
@@ -201,6 +201,9 @@ def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, 
     c.init_params = init_params.data_ptr()
     c.debug_grad = debug_grad.data_ptr() if debug_grad is not None else None
     c.debug_targets = debug_targets.data_ptr() if debug_targets is not None else None
+    if eval_tiles is not None:
+        _require_cuda(eval_tiles, "eval_tiles", torch.int32)
+        c.eval_tiles, c.n_eval_tiles = eval_tiles.data_ptr(), int(eval_tiles.numel())
     return c
 
 

@@ -57,7 +57,8 @@ class FFConfig(ctypes.Structure):
     _fields_ = [("tile_rays", c_int32_2), ("r_near", ctypes.c_double), ("n_samples", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("cell_size", ctypes.c_double), ("samples", ctypes.c_void_p), ("init_params", ctypes.c_void_p),
-                ("debug_grad", ctypes.c_void_p), ("debug_targets", ctypes.c_void_p)]
+                ("debug_grad", ctypes.c_void_p), ("debug_targets", ctypes.c_void_p),
+                ("eval_tiles", ctypes.c_void_p), ("n_eval_tiles", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported function

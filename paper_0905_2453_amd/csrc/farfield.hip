@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     __shared__ int s_cells[4];
     __shared__ uint32_t s_lost;
 
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = f.eval_tiles ? (uint32_t)f.eval_tiles[blockIdx.x] : blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
     double lo[2], hi[2], c[2], hw[2];
     int64_t i0[2];
@@ -790,10 +790,12 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cells_sort, dim3((g.n_cells + 255) / 256), dim3(256), 0, s, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t grid = (uint32_t)(f.eval_tiles ? f.n_eval : f.n_tiles);
+    if (grid == 0) return hipSuccess;
     if (f.ray_y)
-        hipLaunchKernelGGL((k_surrogate<true>), dim3((uint32_t)f.n_tiles), dim3(256), 0, s, f, g);
+        hipLaunchKernelGGL((k_surrogate<true>), dim3(grid), dim3(256), 0, s, f, g);
     else
-        hipLaunchKernelGGL((k_surrogate<false>), dim3((uint32_t)f.n_tiles), dim3(256), 0, s, f, g);
+        hipLaunchKernelGGL((k_surrogate<false>), dim3(grid), dim3(256), 0, s, f, g);
     return hipGetLastError();
 }
 

@@ -729,17 +729,31 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     if (g.n_tiles == 0) return RS_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // the model must have been fitted for this grid, tiling and configuration
+    if (cfg->n_eval_tiles < 0 || (cfg->n_eval_tiles > 0 && !cfg->eval_tiles))
+        return fail(RS_EINVAL, "eval_tiles / n_eval_tiles inconsistent");
     uint64_t hdr[2] = {0, 0};
+    std::vector<int32_t> tl(cfg->eval_tiles ? (size_t)cfg->n_eval_tiles : 0);
     hipError_t e = hipMemcpyAsync(hdr, model, sizeof hdr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !tl.empty())
+        e = hipMemcpyAsync(tl.data(), cfg->eval_tiles, tl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return dev_fail(e, "model header read");
     if (hdr[0] != rs::kModelMagic || hdr[1] != ff_hash(job, cfg))
         return fail(RS_ENOTFIT, "model was not fitted for this job and configuration");
+    {
+        std::vector<char> seen((size_t)g.n_tiles, 0);
+        for (int32_t t : tl) {
+            if (t < 0 || t >= g.n_tiles || seen[(size_t)t]) return fail(RS_EINVAL, "bad or repeated tile index %d", t);
+            seen[(size_t)t] = 1;
+        }
+    }
     rs::FarArgs f = far_args(job, cfg, g);
     f.model = const_cast<uint8_t *>(static_cast<const uint8_t *>(model));
     f.ray_y = opts ? opts->ray_y : nullptr;
     f.ray_pix = opts ? opts->ray_pix : nullptr;
     f.affine_only = (opts && (opts->flags & RS_FLAG_AFFINE_ONLY)) ? 1 : 0;
+    f.eval_tiles = cfg->eval_tiles;
+    f.n_eval = cfg->eval_tiles ? cfg->n_eval_tiles : g.n_tiles;
     uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     const size_t cells = (size_t)(ncx * ncy);
     rs::CellArgs cg{};

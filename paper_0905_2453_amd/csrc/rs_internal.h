@@ -88,6 +88,8 @@ struct FarArgs {
     double *ray_y;
     int32_t *ray_pix;
     int32_t affine_only;
+    const int32_t *eval_tiles;    // optional tile list (blockIdx.x -> tile)
+    int64_t n_eval;
 };
 
 // Uniform grid of lens cells around the ray window (near-field candidates).

@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--lens-tile", type=int, default=0)
     ap.add_argument("--fp32-run", type=int, default=0)
     ap.add_argument("--map-window", type=int, default=0)
+    ap.add_argument("--jitter-seed", type=int, default=None,
+                    help="one seeded random ray per cell (Monte Carlo placement) instead of cell centres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="default workload: skip the batched and learned far-field measurements")
@@ -342,7 +344,7 @@ def main():
     opts.lens_tile = args.lens_tile
     opts.fp32_run, opts.map_window = args.fp32_run, args.map_window
     job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
-                     counts, lost)
+                     counts, lost, jitter_seed=args.jitter_seed)
     ws = torch.empty(P.workspace_bytes(job, opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -391,7 +393,8 @@ def main():
         "config": {"workload": w.name, "n_lens": w.n_lens, "ray_grid": list(w.grid_n),
                    "map": list(w.map_n), "kappa_star": w.kappa_star, "kappa_c": w.kappa_c, "gamma": w.gamma,
                    "masses": "unit" if args.workload == "small" else "power law 2.35 on [0.1,1]",
-                   "fp64_combine": True, "parallelism": "1 GPU"},
+                   "fp64_combine": True, "parallelism": "1 GPU",
+                   "rays": "cell centres" if args.jitter_seed is None else f"jittered, seed {args.jitter_seed}"},
         "gflops": value * FLOP_PER_INTERACTION / 1e9,
         "rays_per_s": w.n_rays * args.steps / wall,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

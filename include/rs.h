@@ -13,9 +13,10 @@
  *
  * Conventions shared by every entry point
  *   - Lengths are in Einstein radii of a unit-mass lens.
- *   - Rays sit at the centres of a regular grid: coordinate i of axis k is the
- *     float32 rounding of lo_k + (i + 1/2) (hi_k - lo_k) / n_k, evaluated in
- *     FP64 as t = (hi-lo)/n, v = (i + 0.5) t, w = lo + v (no fused operations).
+ *   - Rays sit one per cell of a regular grid, at the cell centre or at a seeded
+ *     random point of the cell (rs_raygrid): coordinate i of axis k is the float32
+ *     rounding of lo_k + (i + u) (hi_k - lo_k) / n_k, evaluated in FP64 as
+ *     t = (hi-lo)/n, v = (i + u) t, w = lo + v (no fused operations).
  *   - The deflection is summed in float32 over runs of consecutive lenses
  *     (lens-index order); each run's partial sum is added to a per-ray FP64
  *     accumulator (eq. 5 with FP64 combination).  The lens equation and the
@@ -78,15 +79,26 @@ typedef struct {
 } rs_macro;
 
 /*
- * Image-plane ray grid: the rectangle [lo, hi) cut into n[0] x n[1] cells, one
- * ray per cell centre.  Only the window [win_lo, win_lo + win_n) is shot by a
- * call, so a large grid can be streamed in pieces whose ray positions do not
- * depend on the split.
+ * Image-plane ray grid: the rectangle [lo, hi) cut into n[0] x n[1] cells, one ray per cell.
+ * Only the window [win_lo, win_lo + win_n) is shot by a call, so a large grid can be streamed
+ * in pieces whose ray positions do not depend on the split.
+ *
+ * Ray placement.  jitter = 0: the cell centre (u_k = 1/2).  jitter = 1: one uniformly random
+ * point per cell, the paper's Monte Carlo ray positions (section 2.1, 2.2) stratified by cell:
+ * for the ray of cell (i1, i2), r = i2 * n[0] + i1, and axis k (s = 8 for axis 1, 9 for axis 2)
+ *     key = mix(jitter_seed * G xor (s << 32)),  h = mix(key + (r + 1) * G),
+ *     u_k = (h >> 11) * 2^-53,  G = 0x9E3779B97F4A7C15,
+ * with mix the SplitMix64 output function (Steele, Lea & Flood 2014; 64-bit wrapping).
+ * In both cases coordinate k is the float32 rounding of lo_k + (i_k + u_k) t_k, t_k =
+ * (hi_k - lo_k) / n_k, evaluated in FP64 as v = ((double)i_k + u_k) t_k, w = lo_k + v.
  */
 typedef struct {
     double lo[2], hi[2];
     int64_t n[2];
     int64_t win_lo[2], win_n[2];
+    uint64_t jitter_seed;
+    int32_t jitter;             /* 0: cell centres, 1: random point per cell */
+    int32_t reserved;           /* must be 0 */
 } rs_raygrid;
 
 /* Source-plane map: the rectangle [lo, hi) cut into n[0] x n[1] half-open pixels. */

@@ -36,11 +36,17 @@ def lib():
         L.orc_deflect_points.argtypes = [_P, ctypes.c_int64, _P, ctypes.c_int64, _P]
         L.orc_deflect_points.restype = None
         L.orc_trace.argtypes = [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _P, _P, _P,
-                                _P, _P, _P, _P, ctypes.c_int64, _P, _P]
+                                ctypes.c_uint64, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int64, _P, _P]
         L.orc_trace.restype = None
         L.orc_shoot.argtypes = [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _P, _P, _P,
-                                _P, _P, _P, _P, _P, _P, _P]
+                                ctypes.c_uint64, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]
         L.orc_shoot.restype = ctypes.c_int64
+        L.orc_mix64.argtypes = [ctypes.c_uint64]
+        L.orc_mix64.restype = ctypes.c_uint64
+        L.orc_jitter_u.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int64]
+        L.orc_jitter_u.restype = ctypes.c_double
+        L.orc_ray_positions.argtypes = [_P, _P, _P, ctypes.c_uint64, ctypes.c_int, _P, ctypes.c_int64, _P]
+        L.orc_ray_positions.restype = None
         _lib = L
     return _lib
 
@@ -73,6 +79,21 @@ def deflect(lenses, pts) -> np.ndarray:
     return out
 
 
+def _jitter(w):
+    seed = getattr(w, "jitter_seed", None)
+    return (0, 0) if seed is None else (int(seed) & 0xFFFFFFFFFFFFFFFF, 1)
+
+
+def ray_positions(w, ray_idx) -> np.ndarray:
+    """float32 positions (n x 2) of the listed grid rays (cell centres or jittered)."""
+    glo, ghi, gn, _, _, _ = _geom(w)
+    idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
+    out = np.empty((len(idx), 2), dtype=np.float32)
+    seed, jit = _jitter(w)
+    lib().orc_ray_positions(_ptr(glo), _ptr(ghi), _ptr(gn), seed, jit, _ptr(idx), len(idx), _ptr(out))
+    return out
+
+
 def _geom(w):
     glo = np.array(w.grid_lo, dtype=np.float64)
     ghi = np.array(w.grid_hi, dtype=np.float64)
@@ -90,8 +111,9 @@ def trace(w, ray_idx) -> tuple[np.ndarray, np.ndarray]:
     idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
     y = np.empty((len(idx), 2), dtype=np.float64)
     pix = np.empty(len(idx), dtype=np.int64)
+    seed, jit = _jitter(w)
     lib().orc_trace(_ptr(L), L.shape[0], float(w.kappa_c), float(w.gamma), _ptr(glo), _ptr(ghi),
-                    _ptr(gn), _ptr(mlo), _ptr(mhi), _ptr(mn), _ptr(idx), len(idx), _ptr(y), _ptr(pix))
+                    _ptr(gn), seed, jit, _ptr(mlo), _ptr(mhi), _ptr(mn), _ptr(idx), len(idx), _ptr(y), _ptr(pix))
     return y, pix
 
 
@@ -117,8 +139,9 @@ def shoot(w, window=None) -> tuple[np.ndarray, int]:
     wn = np.array(window[1], dtype=np.int64)
     counts = np.zeros((int(mn[1]), int(mn[0])), dtype=np.uint32)
     lost = np.zeros(1, dtype=np.uint64)
+    seed, jit = _jitter(w)
     lib().orc_shoot(_ptr(L), L.shape[0], float(w.kappa_c), float(w.gamma), _ptr(glo), _ptr(ghi),
-                    _ptr(gn), _ptr(wlo), _ptr(wn), _ptr(mlo), _ptr(mhi), _ptr(mn), _ptr(counts),
+                    _ptr(gn), seed, jit, _ptr(wlo), _ptr(wn), _ptr(mlo), _ptr(mhi), _ptr(mn), _ptr(counts),
                     _ptr(lost))
     return counts, int(lost[0])
 

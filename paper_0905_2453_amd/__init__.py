@@ -58,7 +58,7 @@ def _require_cuda(t, name, dtype=None):
 
 
 def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts, lost,
-             window=None) -> _abi.Job:
+             window=None, jitter_seed=None) -> _abi.Job:
     """Fill an rs_job from device tensors and plain numbers (no copies)."""
     torch = _torch()
     _require_cuda(lenses, "lenses", torch.float32)
@@ -84,6 +84,8 @@ def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, m
         j.map.lo[k] = float(map_lo[k])
         j.map.hi[k] = float(map_hi[k])
         j.map.n[k] = int(map_n[k])
+    if jitter_seed is not None:
+        j.grid.jitter, j.grid.jitter_seed = 1, int(jitter_seed) & 0xFFFFFFFFFFFFFFFF
     j.counts = ctypes.c_void_p(counts.data_ptr())
     j.n_lost = ctypes.c_void_p(lost.data_ptr())
     return j
@@ -105,7 +107,7 @@ def shoot_job(job: _abi.Job, workspace, opts: Opts | None = None, stream=None) -
 
 
 def shoot(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts=None,
-          lost=None, window=None, opts: Opts | None = None, workspace=None, stream=None):
+          lost=None, window=None, opts: Opts | None = None, workspace=None, stream=None, jitter_seed=None):
     """Shoot a ray-grid window and add its counts into ``counts`` (int32 view of uint32 bins).
 
     Returns (counts, lost): counts is map_n[1] x map_n[0], lost a 1-element int64 tensor.
@@ -118,7 +120,7 @@ def shoot(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_
     if lost is None:
         lost = torch.zeros(1, dtype=torch.int64, device=dev)
     job = make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts, lost,
-                   window)
+                   window, jitter_seed)
     if workspace is None:
         workspace = torch.empty(workspace_bytes(job, opts), dtype=torch.uint8, device=dev)
     shoot_job(job, workspace, opts, stream)

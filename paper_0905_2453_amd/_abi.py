@@ -35,7 +35,8 @@ class Macro(ctypes.Structure):
 
 class RayGrid(ctypes.Structure):
     _fields_ = [("lo", c_double2), ("hi", c_double2), ("n", c_int64_2), ("win_lo", c_int64_2),
-                ("win_n", c_int64_2)]
+                ("win_n", c_int64_2), ("jitter_seed", ctypes.c_uint64), ("jitter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Map(ctypes.Structure):

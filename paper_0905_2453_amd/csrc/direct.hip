@@ -19,10 +19,10 @@ namespace rs {
 
 namespace {
 
-// Coordinate i of a grid axis (cell centre), FP64 then rounded to float32.
-__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i)
+// Coordinate i of a grid axis at offset u in [0, 1) of its cell, FP64 then rounded to float32.
+__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i, double u = 0.5)
 {
-    double v = ((double)i + 0.5) * t;
+    double v = ((double)i + u) * t;
     double w = lo + v;
     return (float)w;
 }
@@ -57,7 +57,7 @@ struct TileSmem {
 
 // Shoot ray tile `tile` of the job described by `a` with the whole workgroup; `slot` selects
 // the partial map the tile's counts go to.  Every thread of the workgroup must call it.
-template <int K1, int K2, int T, int LT, bool DUMP>
+template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
 __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, uint32_t slot, TileSmem<LT> &sm)
 {
     static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
@@ -77,11 +77,23 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
     const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
     const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
 
-    float x1[K1], x2[K2];
+    // cell-centred rays share x1 down a column and x2 along a row; jittered rays (JIT) have
+    // their own coordinates, xj1 / xj2 per ray slot
+    float x1[K1], x2[K2], xj1[JIT ? R : 1], xj2[JIT ? R : 1];
 #pragma unroll
     for (int i = 0; i < K1; ++i) x1[i] = ray_coord(a.glo1, a.gt1, a.wlo1 + c0 + i);
 #pragma unroll
     for (int b = 0; b < K2; ++b) x2[b] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + b);
+    if constexpr (JIT) {
+#pragma unroll
+        for (int i = 0; i < K1; ++i)
+#pragma unroll
+            for (int b = 0; b < K2; ++b) {
+                const int64_t g1 = a.wlo1 + c0 + i, g2 = a.wlo2 + r0 + b, r = g2 * a.gn1 + g1;
+                xj1[i * K2 + b] = ray_coord(a.glo1, a.gt1, g1, jitter_u(a.jkey1, r));
+                xj2[i * K2 + b] = ray_coord(a.glo2, a.gt2, g2, jitter_u(a.jkey2, r));
+            }
+    }
 
     for (int b = tid; b < kMaxWindow * kMaxWindow; b += kThreads) s_win[b] = 0u;
     if (tid == 0) s_lost = 0u;
@@ -119,7 +131,20 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
 #pragma unroll
             for (int j = 0; j < T; ++j) {
                 const float4 l = L[r + j];
-                if constexpr (FOLD) {
+                if constexpr (JIT) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const float dx = xj1[k] - l.x, dy = xj2[k] - l.y;
+                        const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                        if (j == 0) {
+                            s1[k] = d * dx;
+                            s2[k] = d * dy;
+                        } else {
+                            s1[k] = fmaf(d, dx, s1[k]);
+                            s2[k] = fmaf(d, dy, s2[k]);
+                        }
+                    }
+                } else if constexpr (FOLD) {
                     // shared per column: x1 - x1_i, its square and m (x1 - x1_i);
                     // per row: x2 - x2_i and m (x2 - x2_i)
                     float dx[K1], dx2[K1], mdx[K1], dy[K2], mdy[K2];
@@ -206,8 +231,8 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
         for (int b = 0; b < K2; ++b) {
             const int k = i * K2 + b;
             const bool ok = (c0 + i < a.wn1) && (r0 + b < a.wn2);
-            const double y1 = a.lam1 * (double)x1[i] - A1[k];
-            const double y2 = a.lam2 * (double)x2[b] - A2[k];
+            const double y1 = a.lam1 * (double)(JIT ? xj1[k] : x1[i]) - A1[k];
+            const double y2 = a.lam2 * (double)(JIT ? xj2[k] : x2[b]) - A2[k];
             int p1 = 0, p2 = 0;
             const int kv = pixel_of(y1, y2, a, p1, p2);
             key[k] = ok ? kv : -2;
@@ -296,11 +321,11 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
     if (tid == 0 && s_lost) atomicAdd(a.lost, (unsigned long long)s_lost);
 }
 
-template <int K1, int K2, int T, int LT, bool DUMP>
+template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
 __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 {
     __shared__ TileSmem<LT> sm;
-    shoot_tile<K1, K2, T, LT, DUMP>(a, blockIdx.x, blockIdx.x & (kPartials - 1), sm);
+    shoot_tile<K1, K2, T, LT, DUMP, JIT>(a, blockIdx.x, blockIdx.x & (kPartials - 1), sm);
 }
 
 // Persistent kernel over a table of jobs: each workgroup takes (job, tile) work items from an
@@ -325,7 +350,10 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs b)
             if (b.item_start[mid] <= item) lo = mid;
             else hi = mid - 1;
         }
-        shoot_tile<K1, K2, T, LT, false>(b.jobs[lo], item - b.item_start[lo], 0u, sm);
+        if (b.jobs[lo].jitter)
+            shoot_tile<K1, K2, T, LT, false, true>(b.jobs[lo], item - b.item_start[lo], 0u, sm);
+        else
+            shoot_tile<K1, K2, T, LT, false, false>(b.jobs[lo], item - b.item_start[lo], 0u, sm);
         __syncthreads();
     }
 }
@@ -370,10 +398,14 @@ __global__ void __launch_bounds__(256) k_reduce(const uint32_t *partial, int64_t
 template <int K1, int K2, int T, int LT>
 hipError_t launch_kt(const DirectArgs &a, int64_t n_tiles, hipStream_t s)
 {
-    if (a.ray_y)
-        hipLaunchKernelGGL((k_direct<K1, K2, T, LT, true>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_direct<K1, K2, T, LT, false>), dim3((unsigned)n_tiles), dim3(kThreads), 0, s, a);
+    const dim3 g((unsigned)n_tiles), blk(kThreads);
+    if (a.jitter) {
+        if (a.ray_y) hipLaunchKernelGGL((k_direct<K1, K2, T, LT, true, true>), g, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_direct<K1, K2, T, LT, false, true>), g, blk, 0, s, a);
+    } else {
+        if (a.ray_y) hipLaunchKernelGGL((k_direct<K1, K2, T, LT, true, false>), g, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_direct<K1, K2, T, LT, false, false>), g, blk, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -69,9 +69,9 @@ __device__ __forceinline__ bool is_near(float lx, float ly, const double lo[2], 
     return ex * ex + ey * ey < rn2;
 }
 
-__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i)
+__device__ __forceinline__ float ray_coord(double lo, double t, int64_t i, double u = 0.5)
 {
-    double v = ((double)i + 0.5) * t;
+    double v = ((double)i + u) * t;
     double w = lo + v;
     return (float)w;
 }
@@ -671,8 +671,9 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
         const int ri = 128 * ps + 32 * wave + col;
         const int ix = ri % f.TX, iy = ri / f.TX;
         const bool active = ri < f.TX * f.TY && ix < n[0] && iy < n[1];
-        const float x1 = ray_coord(f.glo1, f.gt1, i0[0] + ix);
-        const float x2 = ray_coord(f.glo2, f.gt2, i0[1] + iy);
+        const int64_t g1 = i0[0] + ix, g2 = i0[1] + iy, rg = g2 * f.gn1 + g1;
+        const float x1 = ray_coord(f.glo1, f.gt1, g1, f.jitter ? jitter_u(f.jkey1, rg) : 0.5);
+        const float x2 = ray_coord(f.glo2, f.gt2, g2, f.jitter ? jitter_u(f.jkey2, rg) : 0.5);
         // far field: network
         float o0 = 0.f, o1 = 0.f;
         if (!f.affine_only) {

@@ -88,6 +88,9 @@ int validate_job(const rs_job *j)
         if (g.win_lo[k] < 0 || g.win_n[k] < 0 || g.win_lo[k] > g.n[k] || g.win_n[k] > g.n[k] - g.win_lo[k])
             return fail(RS_EINVAL, "grid axis %d: window outside the grid", k);
     }
+    if ((g.jitter != 0 && g.jitter != 1) || g.reserved != 0) return fail(RS_EINVAL, "grid: jitter must be 0 or 1");
+    if (g.n[0] > (int64_t(1) << 31) || g.n[1] > (int64_t(1) << 31) || g.n[0] * g.n[1] >= (int64_t(1) << 62))
+        return fail(RS_ERANGE, "grid too large");
     const rs_map &m = j->map;
     for (int k = 0; k < 2; ++k) {
         if (!finite(m.lo[k]) || !finite(m.hi[k]) || !(m.hi[k] > m.lo[k]))
@@ -142,6 +145,10 @@ rs::DirectArgs make_args(const rs_job *job, const Tune &t, uint32_t *partial, in
     const int64_t cols = 64 * (int64_t)t.K1;
     const int64_t rows = (int64_t)rs::kWaves * t.K2;
     a.tiles_x = (int32_t)((g.win_n[0] + cols - 1) / cols);
+    a.gn1 = g.n[0];
+    a.jitter = g.jitter;
+    a.jkey1 = rs::jitter_key(g.jitter_seed, 0);
+    a.jkey2 = rs::jitter_key(g.jitter_seed, 1);
     return a;
 }
 
@@ -453,6 +460,10 @@ rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
     f.mn2 = job->map.n[1];
     f.counts = job->counts;
     f.lost = reinterpret_cast<unsigned long long *>(job->n_lost);
+    f.gn1 = gr.n[0];
+    f.jitter = gr.jitter;
+    f.jkey1 = rs::jitter_key(gr.jitter_seed, 0);
+    f.jkey2 = rs::jitter_key(gr.jitter_seed, 1);
     return f;
 }
 

@@ -34,7 +34,29 @@ struct DirectArgs {
     unsigned long long *lost;
     double *ray_y;          // optional per-ray dump (window-relative index)
     int32_t *ray_pix;
+    int64_t gn1;            // full grid width (ray index for the jitter hash)
+    uint64_t jkey1, jkey2;  // per-axis jitter keys; jitter = 0: cell centres
+    int32_t jitter;
 };
+
+// SplitMix64 output function (64-bit wrapping arithmetic).
+__host__ __device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+// key of the jitter stream of axis k (0 or 1) under `seed`
+__host__ __device__ inline uint64_t jitter_key(uint64_t seed, int k)
+{
+    return mix64(seed * kGolden ^ ((uint64_t)(8 + k) << 32));
+}
+// offset in [0, 1) of the ray with grid index r along the axis whose key is `key`
+__device__ __forceinline__ double jitter_u(uint64_t key, int64_t r)
+{
+    return (double)(mix64(key + (uint64_t)(r + 1) * kGolden) >> 11) * 0x1.0p-53;
+}
 
 // A table of jobs for the persistent batched kernel (all in device memory).
 struct BatchArgs {
@@ -90,6 +112,9 @@ struct FarArgs {
     int32_t affine_only;
     const int32_t *eval_tiles;    // optional tile list (blockIdx.x -> tile)
     int64_t n_eval;
+    int64_t gn1;                  // full grid width, jitter keys and switch (as DirectArgs)
+    uint64_t jkey1, jkey2;
+    int32_t jitter;
 };
 
 // Uniform grid of lens cells around the ray window (near-field candidates).

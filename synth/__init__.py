@@ -190,6 +190,7 @@ class Workload:
     kappa_star: float = 0.0
     lens_radius: float = 0.0
     extra: dict = field(default_factory=dict)
+    jitter_seed: int | None = None    # None: rays at cell centres; else one seeded random ray per cell
 
     @property
     def n_rays(self) -> int:

@@ -36,12 +36,30 @@ def test_header_functions_exported():
     assert sorted(e[0] for e in _abi.EXPORTS) == names
 
 
-def test_struct_layout_matches_header_sizes():
+def test_struct_layout_matches_header(tmp_path):
+    # compile the C header and compare every field offset and struct size with the ctypes mirror
+    import subprocess
     from paper_0905_2453_amd import _abi
-    assert ctypes.sizeof(_abi.Macro) == 16
-    assert ctypes.sizeof(_abi.RayGrid) == 16 + 16 + 16 + 16 + 16
-    assert ctypes.sizeof(_abi.Map) == 16 + 16 + 8
-    assert ctypes.sizeof(_abi.Opts) == 5 * 4 + 4 + 8 + 8 + 8
+    structs = {"rs_macro": _abi.Macro, "rs_raygrid": _abi.RayGrid, "rs_map": _abi.Map, "rs_job": _abi.Job,
+               "rs_opts": _abi.Opts, "rs_ff_config": _abi.FFConfig}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rs.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def _job(**kw):

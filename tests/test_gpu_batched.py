@@ -32,6 +32,8 @@ def _batch(seed=3, scale=8):
                              (200, 150), (-5.0, -5.0), (5.0, 5.0), (64, 48))
     jobs[1].extra["window"] = ((5, 5), (0, 10))
     jobs[2].extra["window"] = ((3, 11), (jobs[2].grid_n[0] - 7, jobs[2].grid_n[1] - 19))
+    jobs[3].jitter_seed = 1234          # one Monte Carlo (jittered) job in the batch
+    jobs[2].jitter_seed = 77
     return jobs
 
 
@@ -43,7 +45,7 @@ def _jobs_on_device(torch, P, ws_list):
         counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
         lost = torch.zeros(1, dtype=torch.int64, device=dev)
         j = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
-                       w.map_n, counts, lost, window=w.extra.get("window"))
+                       w.map_n, counts, lost, window=w.extra.get("window"), jitter_seed=w.jitter_seed)
         out.append((j, lenses, counts, lost))
     return out
 

@@ -52,7 +52,7 @@ def run(w, opts=None, window=None, dump=False, lenses=None):
         o.ray_y = ry.data_ptr()
         o.ray_pix = rp.data_ptr()
     counts, lost = P.shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
-                           w.map_n, window=window, opts=o)
+                           w.map_n, window=window, opts=o, jitter_seed=w.jitter_seed)
     torch.cuda.synchronize()
     out = (counts.cpu().numpy().view(np.uint32), int(lost.item()))
     if dump:
@@ -254,3 +254,53 @@ def test_paper_scale_sampled_parity():
     assert est <= SWITCH_TOL
     assert abs(slope) < 1.5e-9
     assert nd <= 4
+
+
+# ---------------------------------------------------------------- jittered (Monte Carlo) rays
+
+def test_jittered_positions_bit_identical_to_oracle():
+    # no lenses, no macro term: y = x, so the kernel's FP64 y is its float32 ray position
+    w = synth.Workload("pos", np.zeros((0, 4), np.float32), 0.0, 0.0, (-120.0, -12.0), (120.0, 12.0), (777, 301),
+                       (-130.0, -13.0), (130.0, 13.0), (10, 10), jitter_seed=2 ** 40 + 17)
+    counts, lost, ry, rp = run(w, dump=True)
+    xy = oracle.ray_positions(w, np.arange(w.n_rays)).astype(np.float64)
+    assert np.array_equal(ry, xy)
+    assert lost == 0 and int(counts.sum()) == w.n_rays
+
+
+def test_jittered_small_workload_parity():
+    w = synth.workload_small(seed=6)
+    w.jitter_seed = 99
+    counts, lost, ry, rp = run(w, dump=True)
+    assert int(counts.sum()) + lost == w.n_rays
+    assert np.array_equal(counts.ravel().astype(np.int64), np.bincount(rp[rp >= 0], minlength=counts.size))
+    _, p_o = oracle.trace_parallel(w, np.arange(w.n_rays))
+    frac, nd = switch_fraction(rp.astype(np.int64), p_o)
+    print(f"jittered small workload: {nd} switches (fraction {frac:.1e})")
+    assert frac <= SWITCH_TOL
+    # jitter moves the rays: the map differs from the cell-centred one
+    w.jitter_seed = None
+    c0, _, _, _ = run(w)
+    assert not np.array_equal(c0, counts)
+
+
+def test_jittered_windows_and_block_shapes_agree():
+    torch = _torch()
+    P = _P()
+    w = synth.workload_small(seed=8)
+    w.jitter_seed = 5
+    ref = run(w, dump=True)
+    for K1, K2 in [(2, 4), (4, 4), (2, 2)]:
+        o = P.Opts()
+        o.block_cols, o.block_rows = K1, K2
+        got = run(w, opts=o, dump=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[2], ref[2]), (K1, K2)
+    dev = torch.device("cuda:0")
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    for (a, b) in [((0, 0), (1000, 411)), ((0, 411), (1000, 589))]:
+        P.shoot(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                counts=counts, lost=lost, window=(a, b), jitter_seed=5)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref[0]) and int(lost.item()) == ref[1]

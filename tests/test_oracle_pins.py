@@ -305,3 +305,71 @@ def test_flop_convention_reproduces_paper_rates():
                 continue
             gflops = 10 * 100 * side * side * 1e6 / (h * 3600) / 1e9
             assert abs(gflops / quoted[col] - 1) < 0.06, (side, col, gflops)
+
+
+# ---------------------------------------------------------------- jittered (Monte Carlo) rays
+
+def test_oracle_splitmix_matches_published_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    G = 0x9E3779B97F4A7C15
+    assert [oracle.lib().orc_mix64((G * (i + 1)) & 0xFFFFFFFFFFFFFFFF) for i in range(3)] == vals
+
+
+def test_oracle_jitter_equals_generator_module_draws():
+    # two independent implementations of the same counter hash (C oracle, numpy generators)
+    for seed in (0, 7, 2 ** 63 + 5):
+        r = np.array([0, 1, 5, 999, 123456789], dtype=np.int64)
+        for k in range(2):
+            c = [oracle.lib().orc_jitter_u(seed, k, int(i)) for i in r]
+            py = [synth.uniform(seed, 8 + k, int(i), 1)[0] for i in r]
+            assert c == py
+
+
+def _jw(seed, n=(300, 200)):
+    return _wl(np.zeros((0, 4)), 0.0, 0.0, (-3.0, -2.0), (3.0, 2.0), n, (-1.0, -1.0), (1.0, 1.0), (8, 8))
+
+
+def test_jittered_rays_lie_in_their_cells_and_are_uniform():
+    w = _jw(3)
+    w.jitter_seed = 3
+    idx = np.arange(w.n_rays)
+    xy = oracle.ray_positions(w, idx).astype(np.float64)
+    i1, i2 = idx % w.grid_n[0], idx // w.grid_n[0]
+    t1, t2 = 6.0 / 300, 4.0 / 200
+    u1 = (xy[:, 0] + 3.0) / t1 - i1
+    u2 = (xy[:, 1] + 2.0) / t2 - i2
+    eps = 1e-5
+    assert np.all((u1 > -eps) & (u1 < 1 + eps) & (u2 > -eps) & (u2 < 1 + eps))
+    for u in (u1, u2):
+        assert abs(u.mean() - 0.5) < 4 * math.sqrt(1 / 12 / len(u))
+        assert abs(u.var() - 1 / 12) < 0.01
+    assert abs(np.corrcoef(u1, u2)[0, 1]) < 4 / math.sqrt(len(u1))
+    # centres when jitter is off; a different seed moves every ray
+    w.jitter_seed = None
+    c = oracle.ray_positions(w, idx[:50]).astype(np.float64)
+    assert np.allclose(c[:, 0], -3.0 + (i1[:50] + 0.5) * t1, atol=1e-6)
+    w.jitter_seed = 4
+    assert np.all(oracle.ray_positions(w, idx[:50]) != xy[:50].astype(np.float32))
+
+
+def test_jittered_windows_add_up_and_single_lens_magnification():
+    L = np.array([[0.0, 0.0, 1.0, 0.0]], dtype=np.float32)
+    w = _wl(L, 0.0, 0.0, (-4.0, -4.0), (4.0, 4.0), (800, 800), (-2.0, -2.0), (2.0, 2.0), (4, 4))
+    w.jitter_seed = 11
+    full, lost = oracle.shoot_parallel(w)
+    part = np.zeros_like(full)
+    pl = 0
+    for win in (((0, 0), (800, 333)), ((0, 333), (800, 467))):
+        c, l = oracle.shoot(w, win)
+        part += c
+        pl += l
+    assert np.array_equal(part, full) and pl == lost
+    # annulus mean magnification of a point lens from stratified random rays
+    y, _ = oracle.trace_parallel(w, np.arange(w.n_rays))
+    ry = np.hypot(y[:, 0], y[:, 1])
+    cell = (8.0 / 800) ** 2
+    for ua, ub in [(0.2, 0.3), (1.0, 1.5)]:
+        mu = np.sum((ry >= ua) & (ry < ub)) * cell / (math.pi * (ub * ub - ua * ua))
+        ref = (ub * math.sqrt(ub * ub + 4) - ua * math.sqrt(ua * ua + 4)) / (ub * ub - ua * ua)
+        assert abs(mu / ref - 1) < 5e-3

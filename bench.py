@@ -311,6 +311,36 @@ def bench_surrogate(args, which=None, emit=True):
     return out
 
 
+LC_TRACKS, LC_POINTS, LC_SIGMA, LC_LENGTH = 1024, 1024, 0.05, 10.0
+
+
+def bench_light_curves(P, torch, counts, w, n_av, stream, reps=5):
+    """Light curves off the map just shot: LC_TRACKS seeded straight tracks of LC_LENGTH Einstein
+    radii, LC_POINTS points each, Gaussian source of width LC_SIGMA (support 4 sigma)."""
+    import synth
+    dev = counts.device
+    tr = torch.from_numpy(synth.light_tracks(27, LC_TRACKS, w.map_lo, w.map_hi, LC_LENGTH)).to(dev)
+    mu, _ = P.light_curve(counts, w.map_lo, w.map_hi, w.map_n, n_av, tr, LC_POINTS, "gaussian", LC_SIGMA,
+                          stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        P.light_curve(counts, w.map_lo, w.map_hi, w.map_n, n_av, tr, LC_POINTS, "gaussian", LC_SIGMA,
+                      stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pts = LC_TRACKS * LC_POINTS
+    pix = (w.map_hi[0] - w.map_lo[0]) / w.map_n[0]
+    box = (2 * int(np.ceil(4 * LC_SIGMA / pix)) + 1) ** 2          # support bounding box, pixels
+    m = mu.cpu().numpy()
+    return {"kernel": "k_light_curve", "tracks": LC_TRACKS, "points_per_track": LC_POINTS,
+            "source": f"gaussian sigma {LC_SIGMA} (support 4 sigma)", "track_length": LC_LENGTH,
+            "kernel_ms": ms, "points_per_s": pts / (ms * 1e-3), "box_pixels_per_s": pts * box / (ms * 1e-3),
+            "mean_mu": float(np.nanmean(m))}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -404,7 +434,12 @@ def main():
                      "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},
     }
     if args.workload == "paper" and not args.plain_only:
-        print("bench.py: plain direct sum done; batched maps next", file=sys.stderr, flush=True)
+        print("bench.py: plain direct sum done; light curves next", file=sys.stderr, flush=True)
+        # the map now holds `steps` passes of the ray grid, so N_av scales by the same factor
+        nav = ((w.map_hi[0] - w.map_lo[0]) / w.map_n[0]) * ((w.map_hi[1] - w.map_lo[1]) / w.map_n[1]) / (
+            ((w.grid_hi[0] - w.grid_lo[0]) / w.grid_n[0]) * ((w.grid_hi[1] - w.grid_lo[1]) / w.grid_n[1]))
+        out["light_curves"] = bench_light_curves(P, torch, counts, w, nav * args.steps, stream)
+        print("bench.py: batched maps next", file=sys.stderr, flush=True)
         b = bench_batched(argparse.Namespace(**{**vars(args), "steps": 2, "warmup": 1}), emit=False)
         out["batched"] = {k: b[k] for k in ("value", "batched_ms", "separate_launches_ms", "speedup_vs_separate",
                                             "autotuned", "config")}

@@ -251,6 +251,36 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
 int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
                      void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
 
+/*
+ * Light curves (section 1: a source profile moved across the magnification map, each position's
+ * magnification turned into a magnitude change).  Pixel (p1, p2) has centre
+ * c = lo_k + (p_k + 1/2) (hi_k - lo_k) / n_k and magnification N / n_av (eq. 4).  Track t runs
+ * from s = tracks[4t .. 4t+1] to e = tracks[4t+2 .. 4t+3]; its point k of n_points is
+ * y = s + (k / (n_points - 1)) (e - s)  (y = s when n_points = 1).  The source magnification is
+ *   mu = sum_p w_p N_p / (n_av sum_p w_p)
+ * over the map pixels whose centre lies in the profile's support, |c - y|^2 <= support^2, with
+ * w = exp(-|c - y|^2 / (2 sigma^2)) for a Gaussian (support = cutoff sigma, cutoff 0 -> 4) or
+ * w = 1 for a uniform disc (support = radius).  The magnitude change is -2.5 log10(mu).  A point
+ * whose support holds no pixel centre gives NaN.
+ */
+typedef struct {
+    int32_t kind;               /* 0: Gaussian, 1: uniform disc                                */
+    double size;                /* sigma (Gaussian) or radius (disc), source-plane units, > 0  */
+    double cutoff;              /* Gaussian support in sigmas (0 = 4); ignored for a disc      */
+} rs_source;
+
+/*
+ * counts: device map, map->n[1] rows of map->n[0] uint32 (the layout rs_shoot fills).
+ * tracks: device, n_tracks x 4 doubles (start1, start2, end1, end2), finite.
+ * mu, mag: device outputs of n_tracks x n_points doubles, track-major (either may be NULL).
+ * Nothing is allocated; asynchronous on `stream`.  n_tracks = 0 is a no-op.
+ * Errors: RS_EINVAL for a bad map, n_av <= 0, source or sizes; RS_EDEVICE if the launch fails.
+ * A non-finite track coordinate is not detected (the tracks live on the device) and gives NaN.
+ */
+int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,
+                   const double *tracks, int32_t n_tracks, int32_t n_points, double *mu, double *mag,
+                   void *stream);
+
 /* Destroy the cached batch graphs and staged job tables (e.g. before freeing workspaces). */
 void rs_release_graphs(void);
 

@@ -245,3 +245,34 @@ def farfield_eval(job, cfg, model, workspace, opts: Opts | None = None, stream=N
                                   model.numel() * model.element_size(), ctypes.c_void_p(workspace.data_ptr()),
                                   workspace.numel() * workspace.element_size(), _stream_handle(stream),
                                   ctypes.byref(opts) if opts else None))
+
+
+# ---------------------------------------------------------------- light curves
+
+def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gaussian", size=0.1,
+                cutoff=0.0, stream=None):
+    """rs_light_curve: light curves of a source profile along straight tracks over a device map.
+
+    tracks: device float64 tensor (n_tracks, 4) of (start1, start2, end1, end2).
+    Returns (mu, dmag), device float64 tensors of shape (n_tracks, n_points)."""
+    torch = _torch()
+    _require_cuda(counts, "counts")
+    _require_cuda(tracks, "tracks")
+    if counts.numel() != int(map_n[0]) * int(map_n[1]) or counts.element_size() != 4 or not counts.is_contiguous():
+        raise ValueError("counts must be the contiguous map_n[1] x map_n[0] 32-bit map")
+    if tracks.dtype != torch.float64 or tracks.dim() != 2 or tracks.shape[1] != 4 or not tracks.is_contiguous():
+        raise ValueError("tracks must be a contiguous (n_tracks, 4) float64 tensor")
+    m = _abi.Map()
+    for k in range(2):
+        m.lo[k], m.hi[k], m.n[k] = float(map_lo[k]), float(map_hi[k]), int(map_n[k])
+    s = _abi.Source()
+    s.kind = {"gaussian": 0, "disc": 1}[kind]
+    s.size, s.cutoff = float(size), float(cutoff)
+    nt = int(tracks.shape[0])
+    mu = torch.empty((nt, int(n_points)), dtype=torch.float64, device=counts.device)
+    mag = torch.empty_like(mu)
+    _check(lib().rs_light_curve(ctypes.c_void_p(counts.data_ptr()), ctypes.byref(m), float(n_av), ctypes.byref(s),
+                                ctypes.c_void_p(tracks.data_ptr()), nt, int(n_points),
+                                ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mag.data_ptr()),
+                                _stream_handle(stream)))
+    return mu, mag

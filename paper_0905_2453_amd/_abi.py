@@ -62,6 +62,10 @@ class FFConfig(ctypes.Structure):
                 ("eval_tiles", ctypes.c_void_p), ("n_eval_tiles", ctypes.c_int32)]
 
 
+class Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("size", ctypes.c_double), ("cutoff", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every exported function
 EXPORTS = [
     ("rs_status_str", ctypes.c_char_p, [ctypes.c_int]),
@@ -83,6 +87,9 @@ EXPORTS = [
     ("rs_farfield_eval", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig), ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                         ctypes.POINTER(Opts)]),
+    ("rs_light_curve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Map), ctypes.c_double, ctypes.POINTER(Source),
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     ("rs_release_graphs", None, []),
 ]
 

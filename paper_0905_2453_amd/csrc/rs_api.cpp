@@ -785,6 +785,45 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     return e == hipSuccess ? RS_OK : dev_fail(e, "far-field eval launch");
 }
 
+int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,
+                   const double *tracks, int32_t n_tracks, int32_t n_points, double *mu, double *mag,
+                   void *stream)
+{
+    g_err[0] = '\0';
+    if (!map || !src) return fail(RS_EINVAL, "map and source are required");
+    if (n_tracks < 0) return fail(RS_EINVAL, "n_tracks must be >= 0");
+    if (n_points < 1) return fail(RS_EINVAL, "n_points must be >= 1");
+    if ((int64_t)n_tracks * n_points > ((int64_t)1 << 36)) return fail(RS_EINVAL, "too many track points");
+    for (int k = 0; k < 2; ++k)
+        if (!std::isfinite(map->lo[k]) || !std::isfinite(map->hi[k]) || !(map->hi[k] > map->lo[k]) ||
+            map->n[k] <= 0 || map->n[k] > 65536)
+            return fail(RS_EINVAL, "map axis %d invalid", k);
+    if (!(n_av > 0.0) || !std::isfinite(n_av)) return fail(RS_EINVAL, "n_av must be finite and > 0");
+    if (src->kind != 0 && src->kind != 1) return fail(RS_EINVAL, "source kind must be 0 or 1");
+    if (!(src->size > 0.0) || !std::isfinite(src->size)) return fail(RS_EINVAL, "source size must be finite and > 0");
+    if (!(src->cutoff >= 0.0) || !std::isfinite(src->cutoff)) return fail(RS_EINVAL, "cutoff must be finite and >= 0");
+    if (n_tracks == 0) return RS_OK;
+    if (!counts || !tracks) return fail(RS_EINVAL, "counts and tracks are required");
+    rs::LightArgs a{};
+    a.counts = counts;
+    for (int k = 0; k < 2; ++k) {
+        a.lo[k] = map->lo[k];
+        a.w[k] = (map->hi[k] - map->lo[k]) / (double)map->n[k];
+        a.n[k] = map->n[k];
+    }
+    a.n_av = n_av;
+    a.kind = src->kind;
+    a.size = src->size;
+    a.support = src->kind == 0 ? (src->cutoff > 0.0 ? src->cutoff : 4.0) * src->size : src->size;
+    a.tracks = tracks;
+    a.n_tracks = n_tracks;
+    a.n_points = n_points;
+    a.mu = mu;
+    a.mag = mag;
+    const hipError_t e = rs::launch_light_curve(a, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RS_OK : dev_fail(e, "light-curve launch");
+}
+
 void rs_release_graphs(void)
 {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -129,6 +129,22 @@ struct CellArgs {
 hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s);
 hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
 
+// ---------------------------------------------------------------- light curves
+
+struct LightArgs {
+    const uint32_t *counts;
+    double lo[2], w[2];     // map lower corner and pixel size (hi - lo) / n
+    int32_t n[2];
+    double n_av;
+    int32_t kind;           // 0: Gaussian, 1: uniform disc
+    double size, support;   // sigma or radius; support radius
+    const double *tracks;   // n_tracks x (start1, start2, end1, end2), device
+    int32_t n_tracks, n_points;
+    double *mu, *mag;       // n_tracks x n_points each (either may be null)
+};
+
+hipError_t launch_light_curve(const LightArgs &a, hipStream_t s);
+
 // Per-lane ray blocks (K1 columns x K2 rows) compiled into the library.
 bool ray_block_supported(int K1, int K2);
 // Launch the direct-sum kernel for a K1 x K2 ray block per lane, T-lens float32 runs and LT-lens

@@ -299,3 +299,25 @@ def init_params(seed: int) -> np.ndarray:
         n = fan_in * fan_out
         p[off:off + n] = (2.0 * u[off:off + n] - 1.0) * a
     return p.astype(np.float32)
+
+
+STREAM_MAP = 10
+STREAM_TRACKS = 11
+
+
+def count_map(seed: int, n: tuple[int, int], mean: float) -> np.ndarray:
+    """A seeded uint32 count map of n[1] rows x n[0] columns with the given mean and a heavy
+    upper tail (N = floor(4 mean u^3), u uniform), standing in for a magnification map's counts."""
+    u = uniform(seed, STREAM_MAP, 0, int(n[0]) * int(n[1])).reshape(int(n[1]), int(n[0]))
+    return np.floor(4.0 * mean * u ** 3).astype(np.uint32)
+
+
+def light_tracks(seed: int, n_tracks: int, lo: tuple[float, float], hi: tuple[float, float],
+                 length: float) -> np.ndarray:
+    """n_tracks straight tracks (start1, start2, end1, end2): start uniform over [lo, hi), direction
+    uniform in angle, the given length (ends may leave the region)."""
+    u = uniform(seed, STREAM_TRACKS, 0, 3 * n_tracks).reshape(n_tracks, 3)
+    s1 = lo[0] + u[:, 0] * (hi[0] - lo[0])
+    s2 = lo[1] + u[:, 1] * (hi[1] - lo[1])
+    th = 2.0 * np.pi * u[:, 2]
+    return np.stack([s1, s2, s1 + length * np.cos(th), s2 + length * np.sin(th)], 1)

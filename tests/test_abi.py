@@ -41,10 +41,10 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_0905_2453_amd import _abi
     structs = {"rs_macro": _abi.Macro, "rs_raygrid": _abi.RayGrid, "rs_map": _abi.Map, "rs_job": _abi.Job,
-               "rs_opts": _abi.Opts, "rs_ff_config": _abi.FFConfig}
+               "rs_opts": _abi.Opts, "rs_ff_config": _abi.FFConfig, "rs_source": _abi.Source}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rs.h"', "int main(void) {"]
     for cname, py in structs.items():
-        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        lines.append(f'printf("{cname} sizeof() %zu\\n", sizeof({cname}));')
         for fname, _ in py._fields_:
             lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
     lines += ["return 0; }"]
@@ -57,7 +57,7 @@ def test_struct_layout_matches_header(tmp_path):
         a, b, c = line.split()
         got[(a, b)] = int(c)
     for cname, py in structs.items():
-        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        assert got[(cname, "sizeof()")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
@@ -246,3 +246,31 @@ def test_farfield_validation_without_device():
     st = L.rs_farfield_eval(ctypes.byref(j), ctypes.byref(good), ctypes.c_void_p(0x9000), need,
                             ctypes.c_void_p(0xa000), ew, None, ctypes.byref(o))
     assert st == -3
+
+
+def test_light_curve_validation_without_device():
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    m = _abi.Map()
+    for k in range(2):
+        m.lo[k], m.hi[k], m.n[k] = -1.0, 1.0, 64
+
+    def src(kind=0, size=0.1, cutoff=0.0):
+        s = _abi.Source()
+        s.kind, s.size, s.cutoff = kind, size, cutoff
+        return s
+
+    def call(mp=m, n_av=4.0, s=None, nt=3, npts=10, counts=0x1000, tracks=0x2000):
+        s = s if s is not None else src()
+        return L.rs_light_curve(ctypes.c_void_p(counts), ctypes.byref(mp), n_av, ctypes.byref(s),
+                                ctypes.c_void_p(tracks), nt, npts, ctypes.c_void_p(0x3000), None, None)
+
+    bad_map = _abi.Map()
+    for k in range(2):
+        bad_map.lo[k], bad_map.hi[k], bad_map.n[k] = 1.0, 1.0, 64
+    for st in [call(n_av=0.0), call(n_av=float("nan")), call(s=src(kind=2)), call(s=src(size=0.0)),
+               call(s=src(size=float("inf"))), call(s=src(cutoff=-1.0)), call(nt=-1), call(npts=0),
+               call(mp=bad_map), call(counts=0), call(tracks=0)]:
+        assert st == -1
+    assert call(npts=0) == -1 and b"n_points" in L.rs_last_error()
+    assert call(nt=0, counts=0, tracks=0) == 0          # nothing to do: no launch, no device

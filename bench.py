@@ -46,7 +46,9 @@ def parse():
                     help="one seeded random ray per cell (Monte Carlo placement) instead of cell centres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
-                    help="default workload: skip the batched and learned far-field measurements")
+                    help="default workload: skip the light-curve, batched and learned far-field measurements")
+    ap.add_argument("--legs", default="light_curves,batched,farfield,large",
+                    help="default workload: comma-separated extra measurements to run after the plain one")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (HBM counter calibration)")
@@ -433,17 +435,20 @@ def main():
                      "kernel_ms": kernel_s * 1e3,
                      "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},
     }
-    if args.workload == "paper" and not args.plain_only:
+    legs = [] if args.workload != "paper" or args.plain_only else args.legs.split(",")
+    if "light_curves" in legs:
         print("bench.py: plain direct sum done; light curves next", file=sys.stderr, flush=True)
         # the map now holds `steps` passes of the ray grid, so N_av scales by the same factor
         nav = ((w.map_hi[0] - w.map_lo[0]) / w.map_n[0]) * ((w.map_hi[1] - w.map_lo[1]) / w.map_n[1]) / (
             ((w.grid_hi[0] - w.grid_lo[0]) / w.grid_n[0]) * ((w.grid_hi[1] - w.grid_lo[1]) / w.grid_n[1]))
         out["light_curves"] = bench_light_curves(P, torch, counts, w, nav * args.steps, stream)
+    if "batched" in legs:
         print("bench.py: batched maps next", file=sys.stderr, flush=True)
         b = bench_batched(argparse.Namespace(**{**vars(args), "steps": 2, "warmup": 1}), emit=False)
         out["batched"] = {k: b[k] for k in ("value", "batched_ms", "separate_launches_ms", "speedup_vs_separate",
                                             "autotuned", "config")}
-        for which in ("farfield", "large"):
+    for which in ("farfield", "large"):
+        if which in legs:
             print(f"bench.py: learned far field ({which}) next", file=sys.stderr, flush=True)
             r = bench_surrogate(args, which=which, emit=False)
             out[f"surrogate_{which}"] = {k: r[k] for k in ("config", "fit_s", "eval_s", "plain_s_on_judged_tiles",

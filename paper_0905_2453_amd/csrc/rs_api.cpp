@@ -809,9 +809,11 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     for (int k = 0; k < 2; ++k) {
         a.lo[k] = map->lo[k];
         a.w[k] = (map->hi[k] - map->lo[k]) / (double)map->n[k];
+        a.inv_w[k] = (double)map->n[k] / (map->hi[k] - map->lo[k]);
         a.n[k] = map->n[k];
     }
     a.n_av = n_av;
+    a.inv2s2 = 1.0 / (2.0 * src->size * src->size);
     a.kind = src->kind;
     a.size = src->size;
     a.support = src->kind == 0 ? (src->cutoff > 0.0 ? src->cutoff : 4.0) * src->size : src->size;

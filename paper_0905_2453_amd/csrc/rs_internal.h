@@ -134,10 +134,12 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
 struct LightArgs {
     const uint32_t *counts;
     double lo[2], w[2];     // map lower corner and pixel size (hi - lo) / n
+    double inv_w[2];        // n / (hi - lo), for the support's bounding box only
     int32_t n[2];
     double n_av;
     int32_t kind;           // 0: Gaussian, 1: uniform disc
     double size, support;   // sigma or radius; support radius
+    double inv2s2;          // 1 / (2 sigma^2)
     const double *tracks;   // n_tracks x (start1, start2, end1, end2), device
     int32_t n_tracks, n_points;
     double *mu, *mag;       // n_tracks x n_points each (either may be null)

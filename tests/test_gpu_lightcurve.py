@@ -45,9 +45,10 @@ def _compare(mu_g, mag_g, mu_o, mag_o, exact):
         assert np.array_equal(mu_g[ok], mu_o[ok])
     else:
         rel = np.abs(mu_g[ok] - mu_o[ok]) / np.abs(mu_o[ok])
-        assert rel.max() <= MU_RTOL, rel.max()
+        assert np.all(rel <= MU_RTOL), rel.max()
     fin = ok & (mu_o > 0)
-    assert np.abs(mag_g[fin] - mag_o[fin]).max() <= MAG_ATOL
+    assert np.all(np.abs(mag_g[fin] - mag_o[fin]) <= MAG_ATOL)
+    return int(ok.sum())
 
 
 # rectangular map with non-unit, unequal pixels and an offset corner; tracks leave the map
@@ -55,16 +56,19 @@ LO, N = (-3.0, 1.0), (300, 200)
 HI = (LO[0] + 0.05 * N[0], LO[1] + 0.08 * N[1])
 
 
-def test_disc_bit_exact_on_seeded_map():
+@pytest.mark.parametrize("radius", [0.27, 4.0])   # 4.0: box wider than the LDS staging
+def test_disc_bit_exact_on_seeded_map(radius):
     counts = synth.count_map(21, N, 40.0)
     tr = synth.light_tracks(22, 12, LO, HI, 9.0)
-    mu_g, mag_g = _gpu(counts, LO, HI, N, 40.0, tr, 37, "disc", 0.27)
-    mu_o, mag_o = lc.light_curve(counts, LO, HI, N, 40.0, tr, 37, "disc", 0.27)
-    assert np.isnan(mu_o).any() and (~np.isnan(mu_o)).sum() > 300   # some points leave the map
+    mu_g, mag_g = _gpu(counts, LO, HI, N, 40.0, tr, 37, "disc", radius)
+    mu_o, mag_o = lc.light_curve(counts, LO, HI, N, 40.0, tr, 37, "disc", radius)
+    if radius < 1:
+        assert np.isnan(mu_o).any() and (~np.isnan(mu_o)).sum() > 300   # some points leave the map
     _compare(mu_g, mag_g, mu_o, mag_o, exact=True)
 
 
-@pytest.mark.parametrize("sigma,cutoff", [(0.11, 0.0), (0.04, 6.0), (0.9, 3.0)])
+# the last case's support box is wider than the kernel's LDS staging (per-pixel path)
+@pytest.mark.parametrize("sigma,cutoff", [(0.11, 0.0), (0.04, 6.0), (0.9, 3.0), (2.0, 4.0)])
 def test_gaussian_parity_on_seeded_map(sigma, cutoff):
     counts = synth.count_map(23, N, 40.0)
     tr = synth.light_tracks(24, 10, LO, HI, 7.0)
@@ -95,13 +99,15 @@ def test_full_size_sampled_points():
     mu_g, mag_g = _gpu(counts, lo, hi, n, 16.0, tr, 1024, "gaussian", 0.05)
     pick = synth.sample_indices(28, 1024 * 1024, 64)
     ti, ki = pick // 1024, pick % 1024
+    checked = 0
     for t, k in zip(ti, ki):
         f = k / 1023.0
         s1, s2, e1, e2 = tr[t]
         # a one-point track at the sampled position; f is reproduced exactly by the oracle
         one = np.array([[s1 + f * (e1 - s1), s2 + f * (e2 - s2)] * 2])
         mu_o, mag_o = lc.light_curve(counts, lo, hi, n, 16.0, one, 1, "gaussian", 0.05)
-        _compare(mu_g[t:t + 1, k:k + 1], mag_g[t:t + 1, k:k + 1], mu_o, mag_o, exact=False)
+        checked += _compare(mu_g[t:t + 1, k:k + 1], mag_g[t:t + 1, k:k + 1], mu_o, mag_o, exact=False)
+    assert checked >= 40          # most sampled points lie on the map
 
 
 def test_edge_cases():
@@ -112,7 +118,8 @@ def test_edge_cases():
     tr = np.array([[32.0, 24.0, 32.0, 24.0], [-50.0, 5.0, -40.0, 5.0], [10.0, 10.0, 10.0, 10.0]])
     mu_g, mag_g = _gpu(counts, lo, hi, n, 10.0, tr, 3, "disc", 100.0)
     assert np.all(mu_g[0] == counts.astype(np.float64).sum() / (counts.size * 10.0))
-    assert np.isnan(mu_g[1]).all()
+    mu_g, _ = _gpu(counts, lo, hi, n, 10.0, tr[1:2], 3, "disc", 5.0)       # wholly off the map
+    assert np.isnan(mu_g).all()
     mu_g, _ = _gpu(counts, lo, hi, n, 10.0, tr[2:], 2, "disc", 0.3)        # (10, 10) is a pixel corner
     assert np.isnan(mu_g).all()
     # one-point tracks and empty calls

@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="default workload: skip the light-curve, batched and learned far-field measurements")
-    ap.add_argument("--legs", default="light_curves,batched,farfield,large",
+    ap.add_argument("--legs", default="light_curves,zoom,frames,batched,farfield,large",
                     help="default workload: comma-separated extra measurements to run after the plain one")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -343,6 +343,84 @@ def bench_light_curves(P, torch, counts, w, n_av, stream, reps=5):
             "mean_mu": float(np.nanmean(m))}
 
 
+ZOOM_REFINE, ZOOM_LO, ZOOM_HI, ZOOM_N = 4, (-1.25, -1.25), (1.25, 1.25), (256, 256)
+
+
+def bench_zoom(P, torch, w, lenses, stream):
+    """Interactive zoom: the workload's field and shooting region at ZOOM_REFINE x the ray density
+    per axis, a 2.5 x 2.5 Einstein-radius window at 256^2; zoom vs the full fine-grid shoot, whose
+    counts it must equal exactly."""
+    dev = lenses.device
+    fine = (w.grid_n[0] * ZOOM_REFINE, w.grid_n[1] * ZOOM_REFINE)
+    cp = torch.zeros((ZOOM_N[1], ZOOM_N[0]), dtype=torch.int32, device=dev)
+    cz = torch.zeros_like(cp)
+    lp = torch.zeros(1, dtype=torch.int64, device=dev)
+    lz = torch.zeros_like(lp)
+    jp = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, fine, ZOOM_LO, ZOOM_HI, ZOOM_N, cp, lp)
+    jz = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, fine, ZOOM_LO, ZOOM_HI, ZOOM_N, cz, lz)
+    zp = P.zoom_params()
+    ws = torch.empty(max(P.workspace_bytes(jp), P.zoom_workspace_bytes(jz, zp)), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    P.shoot_zoom(jz, zp, ws, stream=stream)            # warm-up (also checks the arguments)
+    torch.cuda.synchronize()
+    cz.zero_()
+    lz.zero_()
+    t_zoom = timed(lambda: P.shoot_zoom(jz, zp, ws, stream=stream))
+    st = P.zoom_stats(ws, stream)
+    t_full = timed(lambda: P.shoot_job(jp, ws, None, stream))
+    exact = bool(torch.equal(cp, cz))
+    rays = fine[0] * fine[1]
+    return {"config": {"field": w.name, "fine_ray_grid": list(fine), "window": [list(ZOOM_LO), list(ZOOM_HI)],
+                       "map": list(ZOOM_N), "cell": "auto (~256 rays, square)"},
+            "zoom_s": t_zoom, "full_fine_s": t_full, "speedup_vs_full": t_full / t_zoom,
+            "tiles_shot_frac": st["tiles_shot"] / max(1, st["tiles"]),
+            "cells_kept_frac": st["cells_kept"] / max(1, st["cells"]),
+            "equal_to_full": exact, "effective_rays_per_s": rays / t_zoom}
+
+
+N_FRAMES, FRAME_SIGMA_V = 8, 0.05
+
+
+def bench_frames(P, torch, w, lenses, stream):
+    """Time-evolving field: N_FRAMES maps of the workload at times 0, 1, ..., stars moving with
+    a velocity dispersion of FRAME_SIGMA_V Einstein radii per unit time per axis, shot as one
+    batch (lens motion applied while staging; nothing is materialised per frame)."""
+    import synth
+    dev = lenses.device
+    vel = torch.from_numpy(synth.lens_velocities(13, w.n_lens, FRAME_SIGMA_V)).to(dev)
+    maps = [torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev) for _ in range(N_FRAMES)]
+    losts = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(N_FRAMES)]
+    jobs = [P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                       maps[k], losts[k], velocities=vel, time=float(k)) for k in range(N_FRAMES)]
+    ws = torch.empty(P.batched_workspace_bytes(jobs), dtype=torch.uint8, device=dev)
+    P.shoot_batched(jobs, ws, stream=stream)       # warm-up: builds the graph
+    torch.cuda.synchronize()
+    for m in maps:
+        m.zero_()
+    for lo in losts:
+        lo.zero_()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    P.shoot_batched(jobs, ws, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    total = sum(int(m.sum().item()) + int(lo.item()) for m, lo in zip(maps, losts))
+    if total != N_FRAMES * w.n_rays:
+        print("bench.py: frame batch lost rays", file=sys.stderr)
+        sys.exit(3)
+    return {"frames": N_FRAMES, "sigma_v": FRAME_SIGMA_V, "frame_times": [0, N_FRAMES - 1], "batch_s": sec,
+            "frames_per_s": N_FRAMES / sec, "interactions_per_s": N_FRAMES * float(w.n_rays) * w.n_lens / sec}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -442,6 +520,15 @@ def main():
         nav = ((w.map_hi[0] - w.map_lo[0]) / w.map_n[0]) * ((w.map_hi[1] - w.map_lo[1]) / w.map_n[1]) / (
             ((w.grid_hi[0] - w.grid_lo[0]) / w.grid_n[0]) * ((w.grid_hi[1] - w.grid_lo[1]) / w.grid_n[1]))
         out["light_curves"] = bench_light_curves(P, torch, counts, w, nav * args.steps, stream)
+    if "zoom" in legs:
+        print("bench.py: interactive zoom next", file=sys.stderr, flush=True)
+        out["zoom"] = bench_zoom(P, torch, w, lenses, stream)
+        if not out["zoom"]["equal_to_full"]:
+            print("bench.py: zoom map differs from the full fine-grid map", file=sys.stderr)
+            sys.exit(3)
+    if "frames" in legs:
+        print("bench.py: time-evolving frames next", file=sys.stderr, flush=True)
+        out["frames"] = bench_frames(P, torch, w, lenses, stream)
     if "batched" in legs:
         print("bench.py: batched maps next", file=sys.stderr, flush=True)
         b = bench_batched(argparse.Namespace(**{**vars(args), "steps": 2, "warmup": 1}), emit=False)

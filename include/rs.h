@@ -116,6 +116,13 @@ typedef struct {
     rs_map map;
     uint32_t *counts;        /* device, map.n[1] * map.n[0], ACCUMULATED (+=)                */
     uint64_t *n_lost;        /* device, one counter, ACCUMULATED (+=)                        */
+    /* Moving lenses (section 5: stars move between frames).  velocities: device, n_lens x
+     * (v1, v2) float32, or NULL for a static field.  The job then shoots the field at `time`:
+     * lens i sits at float32((double)x_i + (double)v_i * time) per axis (FP64, then rounded),
+     * its mass unchanged.  rs_shoot, rs_shoot_batched and rs_shoot_zoom apply it while staging
+     * lenses; the far-field entry points reject it (materialise with rs_advance_lenses). */
+    const float *velocities;
+    double time;
 } rs_job;
 
 /* Flags for rs_opts.flags */
@@ -250,6 +257,45 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
  */
 int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
                      void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
+
+/*
+ * Moving lenses (section 5): out[i] = (float32(x1_i + v1_i t), float32(x2_i + v2_i t), m_i, pad_i),
+ * the same positions a job with `velocities` and `time` shoots.  lenses, velocities (n x 2
+ * float32) and out (n records) are device memory; out may equal lenses.  Asynchronous.
+ */
+int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n, double time, rs_lens *out,
+                      void *stream);
+
+/*
+ * Interactive zoom (section 5: a selected area of a map recomputed at higher detail).
+ * `job` describes the dense problem: job->grid is the fine ray grid (and window) and job->map the
+ * selected source-plane area at the wanted resolution.  The counts added to job->counts are
+ * exactly those rs_shoot(job) would add, bit for bit, but only the rays that can reach the map
+ * are shot: the window is split into culling cells of zoom->cell fine rays; each cell's image
+ * under eq. 6 is bounded from its centre (deflection, its gradient, a second-order remainder
+ * over the lenses beyond three half-diagonals, 2 m / distance for closer lenses, a cell that
+ * holds a lens is always kept) widened by a float32 rounding allowance and zoom->margin, and
+ * only the ray tiles that overlap a cell whose bound meets the map are shot.
+ * *job->n_lost receives only the shot rays that miss the map.  opts as for rs_shoot, except
+ * that per-ray dumps are rejected (RS_EINVAL).
+ */
+typedef struct {
+    int32_t cell[2];   /* fine rays per culling cell along each axis; {0, 0} = about 256 rays,   */
+                       /* square in the image plane                                          */
+    double margin;     /* extra source-plane distance added to every cell's bound, >= 0      */
+} rs_zoom;
+
+/* Workspace bytes for rs_shoot_zoom (0 if the arguments are invalid). */
+size_t rs_zoom_workspace_bytes(const rs_job *job, const rs_zoom *zoom, const rs_opts *opts);
+
+/* Asynchronous on `stream`; nothing is allocated.  Errors as for rs_shoot, plus RS_ERANGE for
+ * more than 2^30 culling cells. */
+int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_t ws_bytes, void *stream,
+                  const rs_opts *opts);
+
+/* Statistics of the last rs_shoot_zoom on this workspace: out = {ray tiles shot, ray tiles in
+ * the window, culling cells kept, culling cells}.  Synchronises `stream`. */
+int rs_zoom_stats(const void *workspace, uint32_t out[4], void *stream);
 
 /*
  * Light curves (section 1: a source profile moved across the magnification map, each position's

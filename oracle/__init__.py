@@ -164,6 +164,19 @@ def shoot_parallel(w, window=None, threads: int = 8) -> tuple[np.ndarray, int]:
     return counts, lost
 
 
+def lenses_at(lenses, velocities, t: float) -> np.ndarray:
+    """Lens records of a moving field at time t (section 5: stars move between frames).
+
+    Reading (the paper names the effect, not a motion model): each lens moves on a straight line
+    at constant velocity, x_i(t) = x_i + v_i t, evaluated in FP64 from the float32 record and
+    velocity, then rounded to the float32 record; masses do not change."""
+    L = np.array(lenses, dtype=np.float32, copy=True).reshape(-1, 4)
+    v = np.asarray(velocities, dtype=np.float32).reshape(-1, 2)
+    for k in range(2):
+        L[:, k] = (L[:, k].astype(np.float64) + v[:, k].astype(np.float64) * float(t)).astype(np.float32)
+    return L
+
+
 def n_av(w) -> float:
     """Rays per source pixel without lensing: pixel area over ray-cell area (eq. 4's N_av)."""
     dx1 = (w.grid_hi[0] - w.grid_lo[0]) / w.grid_n[0]

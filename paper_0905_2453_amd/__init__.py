@@ -58,8 +58,11 @@ def _require_cuda(t, name, dtype=None):
 
 
 def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts, lost,
-             window=None, jitter_seed=None) -> _abi.Job:
-    """Fill an rs_job from device tensors and plain numbers (no copies)."""
+             window=None, jitter_seed=None, velocities=None, time=0.0) -> _abi.Job:
+    """Fill an rs_job from device tensors and plain numbers (no copies).
+
+    velocities: optional device float32 (n_lens, 2) tensor; the job then shoots the field at
+    `time` (lens i at x_i + v_i time)."""
     torch = _torch()
     _require_cuda(lenses, "lenses", torch.float32)
     if lenses.dim() != 2 or lenses.shape[1] != 4:
@@ -88,7 +91,28 @@ def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, m
         j.grid.jitter, j.grid.jitter_seed = 1, int(jitter_seed) & 0xFFFFFFFFFFFFFFFF
     j.counts = ctypes.c_void_p(counts.data_ptr())
     j.n_lost = ctypes.c_void_p(lost.data_ptr())
+    if velocities is not None:
+        _require_cuda(velocities, "velocities", torch.float32)
+        if velocities.shape != (lenses.shape[0], 2):
+            raise ValueError("velocities must be an n_lens x 2 float32 tensor")
+        j.velocities = ctypes.c_void_p(velocities.data_ptr() if lenses.shape[0] else 0)
+        j.time = float(time)
     return j
+
+
+def advance_lenses(lenses, velocities, time, out=None, stream=None):
+    """rs_advance_lenses: the lens records of a moving field at `time` (device tensors)."""
+    torch = _torch()
+    _require_cuda(lenses, "lenses", torch.float32)
+    _require_cuda(velocities, "velocities", torch.float32)
+    if lenses.dim() != 2 or lenses.shape[1] != 4 or velocities.shape != (lenses.shape[0], 2):
+        raise ValueError("lenses must be n x 4 and velocities n x 2 float32")
+    if out is None:
+        out = torch.empty_like(lenses)
+    _check(lib().rs_advance_lenses(ctypes.c_void_p(lenses.data_ptr()), ctypes.c_void_p(velocities.data_ptr()),
+                                   int(lenses.shape[0]), float(time), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_handle(stream)))
+    return out
 
 
 def workspace_bytes(job: _abi.Job, opts: Opts | None = None) -> int:
@@ -104,6 +128,35 @@ def shoot_job(job: _abi.Job, workspace, opts: Opts | None = None, stream=None) -
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().rs_shoot(ctypes.byref(job), ctypes.c_void_p(workspace.data_ptr()), nbytes,
                           _stream_handle(stream), ctypes.byref(opts) if opts else None))
+
+
+def zoom_params(cell=(0, 0), margin=0.0) -> _abi.Zoom:
+    z = _abi.Zoom()
+    z.cell[0], z.cell[1] = int(cell[0]), int(cell[1])
+    z.margin = float(margin)
+    return z
+
+
+def zoom_workspace_bytes(job: _abi.Job, zoom: _abi.Zoom, opts: Opts | None = None) -> int:
+    n = lib().rs_zoom_workspace_bytes(ctypes.byref(job), ctypes.byref(zoom), ctypes.byref(opts) if opts else None)
+    if n == 0:
+        raise ValueError(f"invalid zoom job: {lib().rs_last_error().decode()}")
+    return n
+
+
+def shoot_zoom(job: _abi.Job, zoom: _abi.Zoom, workspace, opts: Opts | None = None, stream=None) -> None:
+    """rs_shoot_zoom: the fine-grid map of job->map, shooting only the ray tiles that can reach it."""
+    _require_cuda(workspace, "workspace")
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().rs_shoot_zoom(ctypes.byref(job), ctypes.byref(zoom), ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                               _stream_handle(stream), ctypes.byref(opts) if opts else None))
+
+
+def zoom_stats(workspace, stream=None) -> dict:
+    """Statistics of the last zoom on `workspace` (synchronises the stream)."""
+    out = (ctypes.c_uint32 * 4)()
+    _check(lib().rs_zoom_stats(ctypes.c_void_p(workspace.data_ptr()), ctypes.byref(out), _stream_handle(stream)))
+    return {"tiles_shot": out[0], "tiles": out[1], "cells_kept": out[2], "cells": out[3]}
 
 
 def shoot(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts=None,

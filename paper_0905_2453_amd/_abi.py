@@ -45,7 +45,8 @@ class Map(ctypes.Structure):
 
 class Job(ctypes.Structure):
     _fields_ = [("lenses", ctypes.c_void_p), ("n_lens", ctypes.c_int64), ("macro", Macro),
-                ("grid", RayGrid), ("map", Map), ("counts", ctypes.c_void_p), ("n_lost", ctypes.c_void_p)]
+                ("grid", RayGrid), ("map", Map), ("counts", ctypes.c_void_p), ("n_lost", ctypes.c_void_p),
+                ("velocities", ctypes.c_void_p), ("time", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -60,6 +61,10 @@ class FFConfig(ctypes.Structure):
                 ("cell_size", ctypes.c_double), ("samples", ctypes.c_void_p), ("init_params", ctypes.c_void_p),
                 ("debug_grad", ctypes.c_void_p), ("debug_targets", ctypes.c_void_p),
                 ("eval_tiles", ctypes.c_void_p), ("n_eval_tiles", ctypes.c_int32)]
+
+
+class Zoom(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32 * 2), ("margin", ctypes.c_double)]
 
 
 class Source(ctypes.Structure):
@@ -87,6 +92,12 @@ EXPORTS = [
     ("rs_farfield_eval", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig), ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                         ctypes.POINTER(Opts)]),
+    ("rs_advance_lenses", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    ("rs_zoom_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(Zoom), ctypes.POINTER(Opts)]),
+    ("rs_shoot_zoom", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Zoom), ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p, ctypes.POINTER(Opts)]),
+    ("rs_zoom_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32 * 4), ctypes.c_void_p]),
     ("rs_light_curve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Map), ctypes.c_double, ctypes.POINTER(Source),
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),

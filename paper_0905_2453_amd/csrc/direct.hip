@@ -13,6 +13,8 @@
 // operations; with one column the interaction keeps the multiply d = m / r^2.  Lenses stream through LDS in tiles of LT records (double buffered); every lane
 // reads the same record, so each LDS read is a broadcast.  Partial sums run in float32 over
 // T consecutive lenses, then are added to a per-ray FP64 accumulator.
+#include <algorithm>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -109,7 +111,7 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             int64_t i = (int64_t)p * kThreads + tid;
-            reg[p] = i < a.n_lens ? a.lenses[i] : pad_lens();
+            reg[p] = i < a.n_lens ? moved_lens(a.lenses[i], a.vel, i, a.time) : pad_lens();
             s_lens[0][p * kThreads + tid] = reg[p];
         }
     }
@@ -122,7 +124,7 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 int64_t i = (t + 1) * LT + (int64_t)p * kThreads + tid;
-                reg[p] = i < a.n_lens ? a.lenses[i] : pad_lens();
+                reg[p] = i < a.n_lens ? moved_lens(a.lenses[i], a.vel, i, a.time) : pad_lens();
             }
         }
         const float4 *L = s_lens[buf];
@@ -328,6 +330,20 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     shoot_tile<K1, K2, T, LT, DUMP, JIT>(a, blockIdx.x, blockIdx.x & (kPartials - 1), sm);
 }
 
+// Persistent direct sum over a list of ray tiles (the tiles a zoom keeps): workgroup g shoots
+// list[g], list[g + grid], ... below *count.
+template <int K1, int K2, int T, int LT, bool JIT>
+__global__ void __launch_bounds__(kThreads) k_direct_list(const DirectArgs a, const uint32_t *list,
+                                                          const uint32_t *count)
+{
+    __shared__ TileSmem<LT> sm;
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        shoot_tile<K1, K2, T, LT, false, JIT>(a, list[i], i & (kPartials - 1), sm);
+        __syncthreads();
+    }
+}
+
 // Persistent kernel over a table of jobs: each workgroup takes (job, tile) work items from an
 // atomic counter until none are left.  Items are numbered job by job in table order (the host
 // orders jobs by decreasing work per tile), so the costliest tiles are taken first.  Counts go
@@ -359,6 +375,14 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs b)
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v) { p[threadIdx.x] = v; }
+
+__global__ void __launch_bounds__(256) k_advance(const float4 *in, const float2 *vel, int64_t n, double time,
+                                                 float4 *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = moved_lens(in[i], vel, i, time);
+}
 
 __global__ void __launch_bounds__(256) k_zero(uint4 *p, int64_t n4)
 {
@@ -420,6 +444,45 @@ hipError_t launch_k(const DirectArgs &a, int T, int LT, int64_t n_tiles, hipStre
         if (T == 8) return launch_kt<K1, K2, 8, 512>(a, n_tiles, s);
         if (T == 16) return launch_kt<K1, K2, 16, 512>(a, n_tiles, s);
         if (T == 32) return launch_kt<K1, K2, 32, 512>(a, n_tiles, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int K1, int K2, int T, int LT>
+hipError_t launch_lt(const DirectArgs &a, const uint32_t *list, const uint32_t *count, int64_t max_tiles,
+                     hipStream_t s)
+{
+    int occ = 0;
+    if (a.jitter) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_list<K1, K2, T, LT, true>, kThreads, 0) !=
+            hipSuccess)
+            occ = 1;
+    } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_list<K1, K2, T, LT, false>, kThreads,
+                                                            0) != hipSuccess) {
+        occ = 1;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t grid = (int64_t)std::max(1, occ) * std::max(1, cus);
+    if (grid > max_tiles) grid = max_tiles;
+    const dim3 g((unsigned)grid), blk(kThreads);
+    if (a.jitter) hipLaunchKernelGGL((k_direct_list<K1, K2, T, LT, true>), g, blk, 0, s, a, list, count);
+    else hipLaunchKernelGGL((k_direct_list<K1, K2, T, LT, false>), g, blk, 0, s, a, list, count);
+    return hipGetLastError();
+}
+
+template <int K1, int K2>
+hipError_t launch_l(const DirectArgs &a, int T, int LT, const uint32_t *list, const uint32_t *count,
+                    int64_t max_tiles, hipStream_t s)
+{
+    if (LT == 256) {
+        if (T == 8) return launch_lt<K1, K2, 8, 256>(a, list, count, max_tiles, s);
+        if (T == 16) return launch_lt<K1, K2, 16, 256>(a, list, count, max_tiles, s);
+        if (T == 32) return launch_lt<K1, K2, 32, 256>(a, list, count, max_tiles, s);
+    } else if (LT == 512) {
+        if (T == 8) return launch_lt<K1, K2, 8, 512>(a, list, count, max_tiles, s);
+        if (T == 16) return launch_lt<K1, K2, 16, 512>(a, list, count, max_tiles, s);
+        if (T == 32) return launch_lt<K1, K2, 32, 512>(a, list, count, max_tiles, s);
     }
     return hipErrorInvalidValue;
 }
@@ -491,6 +554,14 @@ hipError_t launch_batched(const BatchArgs &b, int K1, int K2, int T, int LT, int
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_direct_list(const DirectArgs &a, int K1, int K2, int T, int LT, const uint32_t *list,
+                              const uint32_t *count, int64_t max_tiles, hipStream_t s)
+{
+    if (max_tiles <= 0) return hipSuccess;
+    RS_BLOCK_SWITCH(launch_l, a, T, LT, list, count, max_tiles, s)
+    return hipErrorInvalidValue;
+}
+
 int batched_occupancy(int K1, int K2, int T, int LT)
 {
     RS_BLOCK_SWITCH(occ_b, T, LT)
@@ -501,6 +572,15 @@ hipError_t launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s)
 {
     if (n <= 0 || n > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(n), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const float4 *in, const float2 *vel, int64_t n, double time, float4 *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_advance, dim3((unsigned)blocks), dim3(256), 0, s, in, vel, n, time, out);
     return hipGetLastError();
 }
 

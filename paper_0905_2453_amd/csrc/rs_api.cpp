@@ -33,7 +33,7 @@ int dev_fail(hipError_t e, const char *what)
     return fail(RS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool finite(double v) { return std::isfinite(v); }
+bool is_fin(double v) { return std::isfinite(v); }
 
 constexpr double kMaxCoord = 1.0e12;  // far below the position of the zero-mass padding lenses
 
@@ -77,10 +77,10 @@ int validate_job(const rs_job *j)
     if (!j) return fail(RS_EINVAL, "job is NULL");
     if (j->n_lens < 0) return fail(RS_EINVAL, "n_lens < 0");
     if (j->n_lens > 0 && !j->lenses) return fail(RS_EINVAL, "lenses is NULL with n_lens > 0");
-    if (!finite(j->macro.kappa_c) || !finite(j->macro.gamma)) return fail(RS_EINVAL, "macro not finite");
+    if (!is_fin(j->macro.kappa_c) || !is_fin(j->macro.gamma)) return fail(RS_EINVAL, "macro not finite");
     const rs_raygrid &g = j->grid;
     for (int k = 0; k < 2; ++k) {
-        if (!finite(g.lo[k]) || !finite(g.hi[k]) || !(g.hi[k] > g.lo[k]))
+        if (!is_fin(g.lo[k]) || !is_fin(g.hi[k]) || !(g.hi[k] > g.lo[k]))
             return fail(RS_EINVAL, "grid axis %d: need finite lo < hi", k);
         if (std::fabs(g.lo[k]) > kMaxCoord || std::fabs(g.hi[k]) > kMaxCoord)
             return fail(RS_EINVAL, "grid axis %d: |coordinate| > 1e12", k);
@@ -93,12 +93,13 @@ int validate_job(const rs_job *j)
         return fail(RS_ERANGE, "grid too large");
     const rs_map &m = j->map;
     for (int k = 0; k < 2; ++k) {
-        if (!finite(m.lo[k]) || !finite(m.hi[k]) || !(m.hi[k] > m.lo[k]))
+        if (!is_fin(m.lo[k]) || !is_fin(m.hi[k]) || !(m.hi[k] > m.lo[k]))
             return fail(RS_EINVAL, "map axis %d: need finite lo < hi", k);
         if (m.n[k] <= 0) return fail(RS_EINVAL, "map axis %d: n <= 0", k);
     }
     if ((int64_t)m.n[0] * (int64_t)m.n[1] >= (int64_t(1) << 31))
         return fail(RS_ERANGE, "map has >= 2^31 pixels");
+    if (j->velocities && !is_fin(j->time)) return fail(RS_EINVAL, "time must be finite");
     if (!j->counts) return fail(RS_EINVAL, "counts is NULL");
     if (!j->n_lost) return fail(RS_EINVAL, "n_lost is NULL");
     if (g.win_n[0] * g.win_n[1] >= (int64_t(1) << 31))
@@ -143,12 +144,13 @@ rs::DirectArgs make_args(const rs_job *job, const Tune &t, uint32_t *partial, in
     a.ray_y = opts ? opts->ray_y : nullptr;
     a.ray_pix = opts ? opts->ray_pix : nullptr;
     const int64_t cols = 64 * (int64_t)t.K1;
-    const int64_t rows = (int64_t)rs::kWaves * t.K2;
     a.tiles_x = (int32_t)((g.win_n[0] + cols - 1) / cols);
     a.gn1 = g.n[0];
     a.jitter = g.jitter;
     a.jkey1 = rs::jitter_key(g.jitter_seed, 0);
     a.jkey2 = rs::jitter_key(g.jitter_seed, 1);
+    a.vel = reinterpret_cast<const float2 *>(job->velocities);
+    a.time = job->time;
     return a;
 }
 
@@ -385,6 +387,7 @@ int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g)
     int st = validate_job(job);
     if (st != RS_OK) return st;
     if (!c) return fail(RS_EINVAL, "far-field config is NULL");
+    if (job->velocities) return fail(RS_EINVAL, "far-field jobs take a static field (materialise moving lenses with rs_advance_lenses)");
     if (c->tile_rays[0] <= 0 || c->tile_rays[1] <= 0) return fail(RS_EINVAL, "tile_rays must be > 0");
     if (!(c->r_near > 0.0) || !std::isfinite(c->r_near)) return fail(RS_EINVAL, "r_near must be finite and > 0");
     if (c->n_samples <= 0 || c->n_samples % 1024) return fail(RS_EINVAL, "n_samples must be a positive multiple of 1024");
@@ -554,6 +557,48 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
     if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------- zoom
+
+struct ZoomLayout {
+    int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, tiles = 0;
+    size_t flags_off = 0, list_off = 0, part_off = 0, total = 0;
+};
+
+int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &L)
+{
+    if (!z) return fail(RS_EINVAL, "zoom is NULL");
+    if (z->cell[0] < 0 || z->cell[1] < 0 || z->cell[0] > 65536 || z->cell[1] > 65536)
+        return fail(RS_EINVAL, "zoom cell must be in [0, 65536]");
+    if (!(z->margin >= 0.0) || !is_fin(z->margin)) return fail(RS_EINVAL, "zoom margin must be finite and >= 0");
+    const rs_raygrid &g = job->grid;
+    const double t1 = (g.hi[0] - g.lo[0]) / (double)g.n[0], t2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
+    int64_t c1 = z->cell[0], c2 = z->cell[1];
+    if (c1 == 0 && c2 == 0) {
+        // about 256 fine rays per cell, square in the image plane
+        c1 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(std::sqrt(256.0 * t2 / t1))));
+        c2 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(256.0 / (double)c1)));
+    } else if (c1 == 0 || c2 == 0) {
+        return fail(RS_EINVAL, "zoom cell: give both sizes or neither");
+    }
+    L.c1 = c1;
+    L.c2 = c2;
+    L.ncx = (g.win_n[0] + c1 - 1) / c1;
+    L.ncy = (g.win_n[1] + c2 - 1) / c2;
+    L.cells = L.ncx * L.ncy;
+    if (L.cells > (int64_t(1) << 30)) return fail(RS_ERANGE, "more than 2^30 culling cells; use larger cells");
+    L.tiles = tile_count(job, t);
+    if (L.tiles >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
+    size_t off = 256;
+    L.flags_off = off;
+    off += align256((size_t)L.cells);
+    L.list_off = off;
+    off += align256((size_t)L.tiles * sizeof(uint32_t));
+    L.part_off = off;
+    off += (size_t)(rs::kPartials * partial_stride(job)) * sizeof(uint32_t);
+    L.total = off + 256;
     return RS_OK;
 }
 
@@ -783,6 +828,121 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     e = rs::launch_zero(reinterpret_cast<uint32_t *>(base), (int64_t)(2 * align256(cells * 4) / 4), s);
     if (e == hipSuccess) e = rs::launch_ff_eval(f, cg, s);
     return e == hipSuccess ? RS_OK : dev_fail(e, "far-field eval launch");
+}
+
+size_t rs_zoom_workspace_bytes(const rs_job *job, const rs_zoom *zoom, const rs_opts *opts)
+{
+    Tune t;
+    ZoomLayout L;
+    if (validate_job(job) != RS_OK || resolve_opts(opts, t) != RS_OK || zoom_layout(job, zoom, t, L) != RS_OK)
+        return 0;
+    return L.total;
+}
+
+int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_t ws_bytes, void *stream,
+                  const rs_opts *opts)
+{
+    g_err[0] = '\0';
+    int st = validate_job(job);
+    if (st != RS_OK) return st;
+    Tune t;
+    if ((st = resolve_opts(opts, t)) != RS_OK) return st;
+    if (opts && (opts->ray_y || opts->ray_pix)) return fail(RS_EINVAL, "per-ray dumps are not available in a zoom");
+    ZoomLayout L;
+    if ((st = zoom_layout(job, zoom, t, L)) != RS_OK) return st;
+    if (!workspace) return fail(RS_EINVAL, "workspace is NULL");
+    if (ws_bytes < L.total) return fail(RS_ESMALLBUF, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    if (opts && (opts->flags & RS_FLAG_FAULT_INJECT)) return fail(RS_EDEVICE, "injected fault (RS_FLAG_FAULT_INJECT)");
+
+    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    uint32_t *stats = reinterpret_cast<uint32_t *>(base);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = rs::launch_fill_u32(stats, 4, 0u, s);
+    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 1, 1, (uint32_t)L.tiles, s);
+    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 3, 1, (uint32_t)std::min<int64_t>(L.cells, 0xffffffffll), s);
+    if (e != hipSuccess) return dev_fail(e, "zoom statistics reset");
+    const rs_raygrid &g = job->grid;
+    if (g.win_n[0] == 0 || g.win_n[1] == 0) return RS_OK;
+
+    uint32_t *part = reinterpret_cast<uint32_t *>(base + L.part_off);
+    const int64_t pstride = partial_stride(job);
+    const int64_t bins = (int64_t)job->map.n[0] * job->map.n[1];
+    const rs::DirectArgs a = make_args(job, t, part, pstride, opts);
+
+    rs::ZoomArgs z{};
+    z.lenses = reinterpret_cast<const float4 *>(job->lenses);
+    z.n_lens = job->n_lens;
+    z.glo1 = a.glo1;
+    z.glo2 = a.glo2;
+    z.gt1 = a.gt1;
+    z.gt2 = a.gt2;
+    z.wlo1 = g.win_lo[0];
+    z.wlo2 = g.win_lo[1];
+    z.wn1 = g.win_n[0];
+    z.wn2 = g.win_n[1];
+    z.c1 = L.c1;
+    z.c2 = L.c2;
+    z.ncx = L.ncx;
+    z.ncy = L.ncy;
+    z.tile_cols = 64 * (int64_t)t.K1;
+    z.tile_rows = (int64_t)rs::kWaves * t.K2;
+    z.tiles_x = (g.win_n[0] + z.tile_cols - 1) / z.tile_cols;
+    z.tiles_y = (g.win_n[1] + z.tile_rows - 1) / z.tile_rows;
+    z.lam1 = a.lam1;
+    z.lam2 = a.lam2;
+    z.zlo1 = job->map.lo[0];
+    z.zlo2 = job->map.lo[1];
+    z.zhi1 = job->map.hi[0];
+    z.zhi2 = job->map.hi[1];
+    z.margin = zoom->margin;
+    // one float32 ulp of the largest grid coordinate: float32 ray coordinates lie within half of
+    // it of their FP64 values, and the float32 cell centre within half of it of the true centre
+    const double xmax = std::max(std::max(std::fabs(g.lo[0]), std::fabs(g.hi[0])),
+                                 std::max(std::fabs(g.lo[1]), std::fabs(g.hi[1])));
+    z.pad = std::ldexp(1.0, std::ilogb(std::max(xmax, 1e-30)) - 23);
+    z.xmax = xmax;
+    z.vel = a.vel;
+    z.time = a.time;
+    z.flags = base + L.flags_off;
+    z.list = reinterpret_cast<uint32_t *>(base + L.list_off);
+    z.stats = stats;
+
+    e = rs::launch_zero(part, rs::kPartials * pstride, s);
+    if (e != hipSuccess) return dev_fail(e, "zero partial maps");
+    e = rs::launch_zoom_mark(z, s);
+    if (e != hipSuccess) return dev_fail(e, "zoom culling launch");
+    e = rs::launch_zoom_tiles(z, s);
+    if (e != hipSuccess) return dev_fail(e, "zoom tile list launch");
+    e = rs::launch_direct_list(a, t.K1, t.K2, t.T, t.LT, z.list, stats, L.tiles, s);
+    if (e != hipSuccess) return dev_fail(e, "zoom direct-sum launch");
+    e = rs::launch_reduce(part, bins, pstride, job->counts, s);
+    if (e != hipSuccess) return dev_fail(e, "map reduce launch");
+    return RS_OK;
+}
+
+int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n, double time, rs_lens *out,
+                      void *stream)
+{
+    g_err[0] = '\0';
+    if (n < 0) return fail(RS_EINVAL, "n < 0");
+    if (n == 0) return RS_OK;
+    if (!lenses || !velocities || !out) return fail(RS_EINVAL, "lenses, velocities and out are required");
+    if (!is_fin(time)) return fail(RS_EINVAL, "time must be finite");
+    const hipError_t e = rs::launch_advance(reinterpret_cast<const float4 *>(lenses),
+                                            reinterpret_cast<const float2 *>(velocities), n, time,
+                                            reinterpret_cast<float4 *>(out), reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RS_OK : dev_fail(e, "advance lenses launch");
+}
+
+int rs_zoom_stats(const void *workspace, uint32_t out[4], void *stream)
+{
+    g_err[0] = '\0';
+    if (!workspace || !out) return fail(RS_EINVAL, "workspace and out are required");
+    const void *base = reinterpret_cast<const void *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(out, base, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? RS_OK : dev_fail(e, "zoom statistics read");
 }
 
 int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,

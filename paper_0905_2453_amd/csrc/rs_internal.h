@@ -37,7 +37,20 @@ struct DirectArgs {
     int64_t gn1;            // full grid width (ray index for the jitter hash)
     uint64_t jkey1, jkey2;  // per-axis jitter keys; jitter = 0: cell centres
     int32_t jitter;
+    const float2 *vel;      // lens velocities or null (static field)
+    double time;            // lens i sits at x_i + v_i time
 };
+
+// Lens record i of a field that may move: positions advanced in FP64, rounded to float32.
+__device__ __forceinline__ float4 moved_lens(float4 l, const float2 *vel, int64_t i, double time)
+{
+    if (vel) {
+        const float2 v = vel[i];
+        l.x = (float)((double)l.x + (double)v.x * time);
+        l.y = (float)((double)l.y + (double)v.y * time);
+    }
+    return l;
+}
 
 // SplitMix64 output function (64-bit wrapping arithmetic).
 __host__ __device__ inline uint64_t mix64(uint64_t z)
@@ -128,6 +141,32 @@ struct CellArgs {
 
 hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s);
 hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
+
+// ---------------------------------------------------------------- zoom
+
+struct ZoomArgs {
+    const float4 *lenses;
+    int64_t n_lens;
+    double glo1, glo2, gt1, gt2;        // fine grid origin and spacing
+    int64_t wlo1, wlo2, wn1, wn2;       // fine ray window
+    int64_t c1, c2, ncx, ncy;           // fine rays per culling cell, cells per axis
+    int64_t tiles_x, tiles_y, tile_cols, tile_rows;   // fine ray tiles of the direct-sum launch
+    double lam1, lam2;
+    double zlo1, zlo2, zhi1, zhi2;      // zoom map rectangle
+    double margin, pad, xmax;           // caller margin; float32 coordinate allowance; max |x|
+    const float2 *vel;                  // lens velocities or null
+    double time;
+    uint8_t *flags;                     // ncx * ncy keep flags
+    uint32_t *list;                     // kept tile indices
+    uint32_t *stats;                    // [0] tiles kept (list length), [2] cells kept
+};
+
+hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s);
+hipError_t launch_advance(const float4 *in, const float2 *vel, int64_t n, double time, float4 *out, hipStream_t s);
+hipError_t launch_zoom_tiles(const ZoomArgs &z, hipStream_t s);
+// Persistent direct sum over the tiles listed in list[0 .. *count).
+hipError_t launch_direct_list(const DirectArgs &a, int K1, int K2, int T, int LT, const uint32_t *list,
+                              const uint32_t *count, int64_t max_tiles, hipStream_t s);
 
 // ---------------------------------------------------------------- light curves
 

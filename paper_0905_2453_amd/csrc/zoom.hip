@@ -1,0 +1,165 @@
+// Interactive zoom (section 5: a selected area of a map recomputed at higher ray density).
+//
+// The zoom map is, by definition, the map that shooting EVERY ray of the fine grid would give on
+// the selected source-plane window.  Only rays that can land in the window matter, so the fine
+// grid is split into culling cells and each cell's whole image under the lens equation (eq. 6
+// with the deflection of eq. 2) is bounded from one evaluation at the cell centre c:
+//
+//   y(x) = y(c) + J(c)(x - c) + R(x)     for the lenses at distance >= 3 rho from c
+//                                         (rho = half-diagonal of the cell), with
+//   J = diag(l1, l2) - grad alpha,  grad alpha_i = m_i / r^4 [[f2^2 - f1^2, -2 f1 f2], [-2 f1 f2, f1^2 - f2^2]]
+//   |R| <= rho^2 sum m_i / (r_i - rho)^3 <= rho^2 (3/2)^3 sum m_i / r_i^3    (|d^2 alpha_i| = 2 m / r^3)
+//
+// while a lens closer than 3 rho moves the image by at most |alpha_i(x) - alpha_i(c)| <= 2 m_i / delta_i
+// (delta_i = its distance to the cell rectangle); a lens inside the rectangle leaves the image
+// unbounded.  A cell whose bounding box, widened by a rounding allowance, misses the window cannot
+// contribute and is skipped; the fine ray tiles that overlap a kept cell are shot exactly as the
+// plain path shoots them, so the zoom map equals the full fine-grid map on the window.
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+
+constexpr int kZoomLT = 256;    // lenses per LDS tile
+constexpr int kZoomRun = 16;    // float32 run length before the FP64 combine
+
+__device__ __forceinline__ float4 zoom_pad_lens()
+{
+    return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
+}
+
+// One thread per culling cell.
+__global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z)
+{
+    __shared__ float4 s_lens[2][kZoomLT];
+    const int64_t cell = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool active = cell < z.ncx * z.ncy;
+    const int64_t mx = active ? cell % z.ncx : 0, my = active ? cell / z.ncx : 0;
+    // fine-grid index range of the cell (global indices), its rectangle, centre and half-widths
+    const int64_t g10 = z.wlo1 + mx * z.c1, g11 = z.wlo1 + min((mx + 1) * z.c1, z.wn1);
+    const int64_t g20 = z.wlo2 + my * z.c2, g21 = z.wlo2 + min((my + 1) * z.c2, z.wn2);
+    const double e1lo = z.glo1 + (double)g10 * z.gt1, e1hi = z.glo1 + (double)g11 * z.gt1;
+    const double e2lo = z.glo2 + (double)g20 * z.gt2, e2hi = z.glo2 + (double)g21 * z.gt2;
+    const float cf1 = (float)(0.5 * (e1lo + e1hi)), cf2 = (float)(0.5 * (e2lo + e2hi));
+    // the rectangle around the float32 centre that holds every fine ray's float32 coordinates
+    const double h1 = fmax(fabs(e1lo - (double)cf1), fabs(e1hi - (double)cf1)) + z.pad;
+    const double h2 = fmax(fabs(e2lo - (double)cf2), fabs(e2hi - (double)cf2)) + z.pad;
+    const double rho2 = h1 * h1 + h2 * h2;
+    const float near2 = (float)(9.0 * rho2);
+    const float fh1 = (float)h1, fh2 = (float)h2;
+
+    double A1 = 0.0, A2 = 0.0, Jd = 0.0, Jo = 0.0, C3 = 0.0, P1 = 0.0, D2 = 0.0, nearsum = 0.0;
+    bool inside = false;
+
+    const int tid = threadIdx.x;
+    const int64_t n_tiles = (z.n_lens + kZoomLT - 1) / kZoomLT;
+    if (n_tiles > 0) {
+        const int64_t i = tid;
+        s_lens[0][tid] = i < z.n_lens ? moved_lens(z.lenses[i], z.vel, i, z.time) : zoom_pad_lens();
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        const int buf = (int)(t & 1);
+        float4 nxt = zoom_pad_lens();
+        const bool more = t + 1 < n_tiles;
+        if (more) {
+            const int64_t i = (t + 1) * kZoomLT + tid;
+            if (i < z.n_lens) nxt = moved_lens(z.lenses[i], z.vel, i, z.time);
+        }
+        for (int r = 0; r < kZoomLT; r += kZoomRun) {
+            float s1 = 0.f, s2 = 0.f, sd = 0.f, so = 0.f, sc = 0.f, sp = 0.f, sq = 0.f;
+#pragma unroll
+            for (int j = 0; j < kZoomRun; ++j) {
+                const float4 l = s_lens[buf][r + j];
+                const float f1 = cf1 - l.x, f2 = cf2 - l.y;
+                const float f1s = f1 * f1, f2s = f2 * f2;
+                const float r2 = f1s + f2s;
+                const float s = __builtin_amdgcn_rsqf(r2);
+                const float q = s * s;
+                const float d = l.z * q;
+                s1 = fmaf(d, f1, s1);
+                s2 = fmaf(d, f2, s2);
+                const bool nr = r2 < near2 && l.z != 0.0f;
+                if (nr) {
+                    // near lens: bound its whole variation over the cell by 2 m / delta
+                    const float ex = fmaxf(fabsf(f1) - fh1, 0.0f), ey = fmaxf(fabsf(f2) - fh2, 0.0f);
+                    const float dl2 = ex * ex + ey * ey;
+                    if (dl2 > 0.0f) nearsum += (double)l.z * (double)__builtin_amdgcn_rsqf(dl2);
+                    else inside = true;
+                }
+                const float dq = nr ? 0.0f : d * q;
+                sd = fmaf(dq, f2s - f1s, sd);
+                so = fmaf(dq, f1 * f2, so);
+                sc = fmaf(nr ? 0.0f : d, s, sc);
+                sp = fmaf(nr ? 0.0f : l.z, s, sp);
+                sq += nr ? 0.0f : d;
+            }
+            A1 += (double)s1;
+            A2 += (double)s2;
+            Jd += (double)sd;
+            Jo += (double)so;
+            C3 += (double)sc;
+            P1 += (double)sp;
+            D2 += (double)sq;
+        }
+        if (more) s_lens[buf ^ 1][tid] = nxt;
+        __syncthreads();
+    }
+    if (!active) return;
+
+    // centre image and the bounds, FP64
+    const double y1 = z.lam1 * (double)cf1 - A1, y2 = z.lam2 * (double)cf2 - A2;
+    const double J11 = fabs(z.lam1 - Jd), J22 = fabs(z.lam2 + Jd), J12 = 2.0 * fabs(Jo);
+    const double tay = rho2 * 3.375 * C3;
+    const double nv = 2.0 * nearsum;
+    // rounding allowance: float32 arithmetic of the fine rays and of this centre evaluation
+    const double scale = 1.5 * P1 + nearsum + fabs(z.lam1 * (double)cf1) + fabs(z.lam2 * (double)cf2) +
+                         fabs(y1) + fabs(y2) + z.xmax * 2.25 * D2;
+    const double slack = 1e-5 * scale + z.margin;
+    const double E1 = (J11 * h1 + J12 * h2 + tay + nv + slack) * (1.0 + 1e-6);
+    const double E2 = (J12 * h1 + J22 * h2 + tay + nv + slack) * (1.0 + 1e-6);
+    bool keep = inside || !(fabs(y1) < 1e300 && fabs(y2) < 1e300 && E1 < 1e300 && E2 < 1e300);
+    if (!keep)
+        keep = (y1 + E1 >= z.zlo1) && (y1 - E1 <= z.zhi1) && (y2 + E2 >= z.zlo2) && (y2 - E2 <= z.zhi2);
+    z.flags[cell] = keep ? 1 : 0;
+    if (keep) atomicAdd(&z.stats[2], 1u);
+}
+
+// One thread per fine ray tile: append the tile if any culling cell it overlaps is kept.
+__global__ void __launch_bounds__(256) k_zoom_tiles(const ZoomArgs z)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= z.tiles_x * z.tiles_y) return;
+    const int64_t tx = t % z.tiles_x, ty = t / z.tiles_x;
+    const int64_t c_lo = tx * z.tile_cols, c_hi = min((tx + 1) * z.tile_cols, z.wn1);
+    const int64_t r_lo = ty * z.tile_rows, r_hi = min((ty + 1) * z.tile_rows, z.wn2);
+    bool keep = false;
+    for (int64_t my = r_lo / z.c2; my <= (r_hi - 1) / z.c2 && !keep; ++my)
+        for (int64_t mx = c_lo / z.c1; mx <= (c_hi - 1) / z.c1; ++mx)
+            if (z.flags[my * z.ncx + mx]) {
+                keep = true;
+                break;
+            }
+    if (keep) z.list[atomicAdd(&z.stats[0], 1u)] = (uint32_t)t;
+}
+
+}  // namespace
+
+hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s)
+{
+    const int64_t cells = z.ncx * z.ncy;
+    if (cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((cells + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_zoom_tiles(const ZoomArgs &z, hipStream_t s)
+{
+    const int64_t n = z.tiles_x * z.tiles_y;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zoom_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z);
+    return hipGetLastError();
+}
+
+}  // namespace rs

@@ -321,3 +321,15 @@ def light_tracks(seed: int, n_tracks: int, lo: tuple[float, float], hi: tuple[fl
     s2 = lo[1] + u[:, 1] * (hi[1] - lo[1])
     th = 2.0 * np.pi * u[:, 2]
     return np.stack([s1, s2, s1 + length * np.cos(th), s2 + length * np.sin(th)], 1)
+
+
+STREAM_VEL = 12
+
+
+def lens_velocities(seed: int, n: int, sigma: float) -> np.ndarray:
+    """n x 2 float32 lens velocities, each component normal with standard deviation sigma
+    (Box-Muller on the seeded uniforms)."""
+    u = uniform(seed, STREAM_VEL, 0, 2 * n).reshape(n, 2)
+    r = np.sqrt(-2.0 * np.log1p(-u[:, 0]))
+    th = 2.0 * np.pi * u[:, 1]
+    return (sigma * np.stack([r * np.cos(th), r * np.sin(th)], 1)).astype(np.float32)

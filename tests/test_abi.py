@@ -41,7 +41,7 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_0905_2453_amd import _abi
     structs = {"rs_macro": _abi.Macro, "rs_raygrid": _abi.RayGrid, "rs_map": _abi.Map, "rs_job": _abi.Job,
-               "rs_opts": _abi.Opts, "rs_ff_config": _abi.FFConfig, "rs_source": _abi.Source}
+               "rs_opts": _abi.Opts, "rs_ff_config": _abi.FFConfig, "rs_source": _abi.Source, "rs_zoom": _abi.Zoom}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rs.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof() %zu\\n", sizeof({cname}));')
@@ -274,3 +274,50 @@ def test_light_curve_validation_without_device():
         assert st == -1
     assert call(npts=0) == -1 and b"n_points" in L.rs_last_error()
     assert call(nt=0, counts=0, tracks=0) == 0          # nothing to do: no launch, no device
+
+
+def test_zoom_validation_without_device():
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    j = _job()
+
+    def z(c0=0, c1=0, margin=0.0):
+        r = _abi.Zoom()
+        r.cell[0], r.cell[1], r.margin = c0, c1, margin
+        return r
+
+    need = L.rs_zoom_workspace_bytes(ctypes.byref(j), ctypes.byref(z()), None)
+    assert need > L.rs_workspace_bytes(ctypes.byref(j), None)
+    for bad in (z(-1, 4), z(4, 0), z(0, 4), z(70000, 1), z(margin=-1.0), z(margin=float("nan"))):
+        assert L.rs_zoom_workspace_bytes(ctypes.byref(j), ctypes.byref(bad), None) == 0
+        st = L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(bad), ctypes.c_void_p(0x4000), need, None, None)
+        assert st == -1
+    assert L.rs_shoot_zoom(ctypes.byref(j), None, ctypes.c_void_p(0x4000), need, None, None) == -1
+    assert L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(z()), ctypes.c_void_p(0x4000), need - 1, None, None) == -4
+    assert L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(z()), None, need, None, None) == -1
+    o = _abi.Opts()
+    o.ray_y, o.ray_pix = 0x5000, 0x6000
+    assert L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(z()), ctypes.c_void_p(0x4000), need, None,
+                           ctypes.byref(o)) == -1
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    assert L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(z()), ctypes.c_void_p(0x4000), need, None,
+                           ctypes.byref(o)) == -3
+    assert L.rs_zoom_stats(None, None, None) == -1
+
+
+def test_moving_lens_validation_without_device():
+    P, L = _lib()
+    j = _job()
+    j.velocities = ctypes.c_void_p(0x7000)
+    j.time = float("nan")
+    assert L.rs_workspace_bytes(ctypes.byref(j), None) == 0
+    j.time = 2.0
+    assert L.rs_workspace_bytes(ctypes.byref(j), None) > 0
+    # the far-field closure takes a static field only
+    c = _ffcfg()
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0
+    assert L.rs_advance_lenses(None, None, 5, 1.0, None, None) == -1
+    assert L.rs_advance_lenses(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 5, float("inf"),
+                               ctypes.c_void_p(0x3000), None) == -1
+    assert L.rs_advance_lenses(None, None, 0, 1.0, None, None) == 0

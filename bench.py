@@ -303,6 +303,8 @@ def bench_surrogate(args, which=None, emit=True):
         "fit_s": fit_s, "eval_s": eval_s, "plain_s_on_judged_tiles": plain_s,
         "rays_per_s": {"surrogate_eval": sur_rays_s, "surrogate_end_to_end": e2e_rays_s, "plain": plain_rays_s},
         "speedup_vs_plain": {"eval_only": sur_rays_s / plain_rays_s, "end_to_end": e2e_rays_s / plain_rays_s},
+        # rays per tile at which shooting a tile plainly costs as much as fitting its closure
+        "break_even_rays_per_tile": fit_s * plain_rays_s / n_tiles,
         "map_l1_rel_err": {"surrogate": l1, "affine_only": l1_aff, "tolerance": 0.01},
     }
     if l1 > 0.01:
@@ -381,7 +383,7 @@ def bench_zoom(P, torch, w, lenses, stream):
     return {"config": {"field": w.name, "fine_ray_grid": list(fine), "window": [list(ZOOM_LO), list(ZOOM_HI)],
                        "map": list(ZOOM_N), "cell": "auto (~256 rays, square)"},
             "zoom_s": t_zoom, "full_fine_s": t_full, "speedup_vs_full": t_full / t_zoom,
-            "tiles_shot_frac": st["tiles_shot"] / max(1, st["tiles"]),
+            "ray_slots_shot_frac": st["slots_shot"] / max(1, st["slots"]),
             "cells_kept_frac": st["cells_kept"] / max(1, st["cells"]),
             "equal_to_full": exact, "effective_rays_per_s": rays / t_zoom}
 
@@ -539,7 +541,8 @@ def main():
             print(f"bench.py: learned far field ({which}) next", file=sys.stderr, flush=True)
             r = bench_surrogate(args, which=which, emit=False)
             out[f"surrogate_{which}"] = {k: r[k] for k in ("config", "fit_s", "eval_s", "plain_s_on_judged_tiles",
-                                                            "rays_per_s", "speedup_vs_plain", "map_l1_rel_err")}
+                                                            "rays_per_s", "speedup_vs_plain",
+                                                            "break_even_rays_per_tile", "map_l1_rel_err")}
     if not args.no_cpu_baseline:
         print("bench.py: CPU oracle baseline next", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -259,6 +259,25 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
                      void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
 
 /*
+ * Ray budget (section 1, eq. 4: N_av, the rays per source pixel without lensing, sets the
+ * map's Poisson noise; section 2: rays cover an image region somewhat larger than the
+ * source region).  Plans a ray grid for `map` with at least `n_av` rays per pixel:
+ *   lambda_k = (1 - kappa - gamma, 1 - kappa + gamma), kappa = kappa_star + macro->kappa_c
+ *   (the field's mean lens mapping); half-widths X_k = margin L_k / (2 max(|lambda_k|, 0.05))
+ *   around the preimage of the map centre, c_k / lambda_k (lambda_k floored the same way);
+ *   square cells of side t <= sqrt(pixel area / n_av), t rounded down to a multiple of
+ *   2 ulp32(max |coordinate| + lens_extent) so every ray coordinate sits on that lattice;
+ *   n_k = ceil(2 X_k / t); the centre is snapped to the lattice too.
+ * out receives lo, hi, n, the full window and jitter off; *n_av_out (if not NULL) the planned
+ * pixel area / t^2.  margin 0 means 1.2.  lens_extent: largest |lens coordinate| (0 if unknown).
+ * The lattice bounds a side at about 2^23 rays; near that limit the planned N_av exceeds the
+ * target by more than the usual fraction of a percent.
+ * Errors: RS_EINVAL for invalid arguments; RS_ERANGE if the cell would fall below the lattice.
+ */
+int rs_plan_grid(const rs_map *map, const rs_macro *macro, double kappa_star, double lens_extent, double n_av,
+                 double margin, rs_raygrid *out, double *n_av_out);
+
+/*
  * Moving lenses (section 5): out[i] = (float32(x1_i + v1_i t), float32(x2_i + v2_i t), m_i, pad_i),
  * the same positions a job with `velocities` and `time` shoots.  lenses, velocities (n x 2
  * float32) and out (n records) are device memory; out may equal lenses.  Asynchronous.
@@ -273,15 +292,15 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
  * exactly those rs_shoot(job) would add, bit for bit, but only the rays that can reach the map
  * are shot: the window is split into culling cells of zoom->cell fine rays; each cell's image
  * under eq. 6 is bounded from its centre (deflection, its gradient, a second-order remainder
- * over the lenses beyond three half-diagonals, 2 m / distance for closer lenses, a cell that
- * holds a lens is always kept) widened by a float32 rounding allowance and zoom->margin, and
- * only the ray tiles that overlap a cell whose bound meets the map are shot.
+ * over the lenses beyond three half-diagonals, 2 m / distance for closer lenses; a cell that
+ * holds a lens is always kept), widened by a float32 rounding allowance and zoom->margin; the
+ * rays of the cells whose bound meets the map are shot with the plain path's arithmetic.
  * *job->n_lost receives only the shot rays that miss the map.  opts as for rs_shoot, except
  * that per-ray dumps are rejected (RS_EINVAL).
  */
 typedef struct {
     int32_t cell[2];   /* fine rays per culling cell along each axis; {0, 0} = about 256 rays,   */
-                       /* square in the image plane                                          */
+                       /* square in the image plane, rounded up to whole lane blocks          */
     double margin;     /* extra source-plane distance added to every cell's bound, >= 0      */
 } rs_zoom;
 
@@ -293,9 +312,10 @@ size_t rs_zoom_workspace_bytes(const rs_job *job, const rs_zoom *zoom, const rs_
 int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_t ws_bytes, void *stream,
                   const rs_opts *opts);
 
-/* Statistics of the last rs_shoot_zoom on this workspace: out = {ray tiles shot, ray tiles in
- * the window, culling cells kept, culling cells}.  Synchronises `stream`. */
-int rs_zoom_stats(const void *workspace, uint32_t out[4], void *stream);
+/* Statistics of the last rs_shoot_zoom on this workspace: out = {culling cells kept, culling
+ * cells, ray slots shot, ray slots in all cells} (a ray slot is one ray of a lane block;
+ * blocks at cell and window edges hold masked slots).  Synchronises `stream`. */
+int rs_zoom_stats(const void *workspace, uint64_t out[4], void *stream);
 
 /*
  * Light curves (section 1: a source profile moved across the magnification map, each position's
@@ -313,6 +333,8 @@ typedef struct {
     int32_t kind;               /* 0: Gaussian, 1: uniform disc                                */
     double size;                /* sigma (Gaussian) or radius (disc), source-plane units, > 0  */
     double cutoff;              /* Gaussian support in sigmas (0 = 4); ignored for a disc      */
+    int32_t layout;             /* evaluation layout: 0 = chosen by size, 1 = one lane per     */
+                                /* point, 2 = one wave per point (results agree to rounding)   */
 } rs_source;
 
 /*

@@ -100,6 +100,23 @@ def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, m
     return j
 
 
+def plan_grid(map_lo, map_hi, map_n, n_av, kappa_star=0.0, kappa_c=0.0, gamma=0.0, lens_extent=0.0,
+              margin=0.0):
+    """rs_plan_grid: a ray grid with at least n_av rays per map pixel.
+
+    Returns (grid_lo, grid_hi, grid_n, planned_n_av)."""
+    m = _abi.Map()
+    for k in range(2):
+        m.lo[k], m.hi[k], m.n[k] = float(map_lo[k]), float(map_hi[k]), int(map_n[k])
+    mac = _abi.Macro()
+    mac.kappa_c, mac.gamma = float(kappa_c), float(gamma)
+    g = _abi.RayGrid()
+    nav = ctypes.c_double()
+    _check(lib().rs_plan_grid(ctypes.byref(m), ctypes.byref(mac), float(kappa_star), float(lens_extent),
+                              float(n_av), float(margin), ctypes.byref(g), ctypes.byref(nav)))
+    return (g.lo[0], g.lo[1]), (g.hi[0], g.hi[1]), (int(g.n[0]), int(g.n[1])), nav.value
+
+
 def advance_lenses(lenses, velocities, time, out=None, stream=None):
     """rs_advance_lenses: the lens records of a moving field at `time` (device tensors)."""
     torch = _torch()
@@ -154,9 +171,9 @@ def shoot_zoom(job: _abi.Job, zoom: _abi.Zoom, workspace, opts: Opts | None = No
 
 def zoom_stats(workspace, stream=None) -> dict:
     """Statistics of the last zoom on `workspace` (synchronises the stream)."""
-    out = (ctypes.c_uint32 * 4)()
+    out = (ctypes.c_uint64 * 4)()
     _check(lib().rs_zoom_stats(ctypes.c_void_p(workspace.data_ptr()), ctypes.byref(out), _stream_handle(stream)))
-    return {"tiles_shot": out[0], "tiles": out[1], "cells_kept": out[2], "cells": out[3]}
+    return {"cells_kept": out[0], "cells": out[1], "slots_shot": out[2], "slots": out[3]}
 
 
 def shoot(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, counts=None,
@@ -303,7 +320,7 @@ def farfield_eval(job, cfg, model, workspace, opts: Opts | None = None, stream=N
 # ---------------------------------------------------------------- light curves
 
 def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gaussian", size=0.1,
-                cutoff=0.0, stream=None):
+                cutoff=0.0, stream=None, layout=0):
     """rs_light_curve: light curves of a source profile along straight tracks over a device map.
 
     tracks: device float64 tensor (n_tracks, 4) of (start1, start2, end1, end2).
@@ -321,6 +338,7 @@ def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gau
     s = _abi.Source()
     s.kind = {"gaussian": 0, "disc": 1}[kind]
     s.size, s.cutoff = float(size), float(cutoff)
+    s.layout = {0: 0, 1: 1, 2: 2, "auto": 0, "lanes": 1, "waves": 2}[layout]
     nt = int(tracks.shape[0])
     mu = torch.empty((nt, int(n_points)), dtype=torch.float64, device=counts.device)
     mag = torch.empty_like(mu)

@@ -68,7 +68,8 @@ class Zoom(ctypes.Structure):
 
 
 class Source(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("size", ctypes.c_double), ("cutoff", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("size", ctypes.c_double), ("cutoff", ctypes.c_double),
+                ("layout", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported function
@@ -92,12 +93,15 @@ EXPORTS = [
     ("rs_farfield_eval", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(FFConfig), ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                         ctypes.POINTER(Opts)]),
+    ("rs_plan_grid", ctypes.c_int, [ctypes.POINTER(Map), ctypes.POINTER(Macro), ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.POINTER(RayGrid),
+                                    ctypes.POINTER(ctypes.c_double)]),
     ("rs_advance_lenses", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     ("rs_zoom_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(Zoom), ctypes.POINTER(Opts)]),
     ("rs_shoot_zoom", ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Zoom), ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p, ctypes.POINTER(Opts)]),
-    ("rs_zoom_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32 * 4), ctypes.c_void_p]),
+    ("rs_zoom_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64 * 4), ctypes.c_void_p]),
     ("rs_light_curve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Map), ctypes.c_double, ctypes.POINTER(Source),
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),

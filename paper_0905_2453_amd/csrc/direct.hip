@@ -57,10 +57,13 @@ struct TileSmem {
     uint32_t lost;
 };
 
-// Shoot ray tile `tile` of the job described by `a` with the whole workgroup; `slot` selects
-// the partial map the tile's counts go to.  Every thread of the workgroup must call it.
+// Shoot one block of rays per lane with the whole workgroup: lane rays are the window-relative
+// columns c0 .. c0 + K1 - 1 and rows r0 .. r0 + K2 - 1; a ray counts only when its column is
+// below cmax and its row below rmax.  `slot` selects the partial map the counts go to.  Every
+// thread of the workgroup must call it.
 template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
-__device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, uint32_t slot, TileSmem<LT> &sm)
+__device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int64_t r0, int64_t cmax, int64_t rmax,
+                                           uint32_t slot, TileSmem<LT> &sm)
 {
     static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
     constexpr int PER = LT / kThreads;
@@ -74,10 +77,6 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int tx = (int)(tile % (uint32_t)a.tiles_x);
-    const int ty = (int)(tile / (uint32_t)a.tiles_x);
-    const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
-    const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
 
     // cell-centred rays share x1 down a column and x2 along a row; jittered rays (JIT) have
     // their own coordinates, xj1 / xj2 per ray slot
@@ -232,7 +231,7 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
 #pragma unroll
         for (int b = 0; b < K2; ++b) {
             const int k = i * K2 + b;
-            const bool ok = (c0 + i < a.wn1) && (r0 + b < a.wn2);
+            const bool ok = (c0 + i < cmax) && (r0 + b < rmax);
             const double y1 = a.lam1 * (double)(JIT ? xj1[k] : x1[i]) - A1[k];
             const double y2 = a.lam2 * (double)(JIT ? xj2[k] : x2[b]) - A2[k];
             int p1 = 0, p2 = 0;
@@ -323,6 +322,19 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
     if (tid == 0 && s_lost) atomicAdd(a.lost, (unsigned long long)s_lost);
 }
 
+// Ray tile `tile` of the window: (64 K1) columns x (4 K2) rows, lane l of wave w holding the
+// K1 x K2 block at columns c0 + K1 l, rows r0 + K2 w.
+template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
+__device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, uint32_t slot, TileSmem<LT> &sm)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tx = (int)(tile % (uint32_t)a.tiles_x);
+    const int ty = (int)(tile / (uint32_t)a.tiles_x);
+    const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
+    const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
+    shoot_rays<K1, K2, T, LT, DUMP, JIT>(a, c0, r0, a.wn1, a.wn2, slot, sm);
+}
+
 template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
 __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 {
@@ -330,16 +342,31 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
     shoot_tile<K1, K2, T, LT, DUMP, JIT>(a, blockIdx.x, blockIdx.x & (kPartials - 1), sm);
 }
 
-// Persistent direct sum over a list of ray tiles (the tiles a zoom keeps): workgroup g shoots
-// list[g], list[g + grid], ... below *count.
+// Persistent direct sum over the lane blocks of a list of culling cells (the cells a zoom
+// keeps).  Cell q of the list covers window columns [mx c1, (mx + 1) c1) and rows
+// [my c2, (my + 1) c2) (clipped to the window); it is cut into S = sx sy lane blocks of K1
+// columns x K2 rows, and block j of cell list[i] is lane slot i S + j.  Workgroup g takes
+// slots g 256 .. g 256 + 255, then g + grid, ...
 template <int K1, int K2, int T, int LT, bool JIT>
-__global__ void __launch_bounds__(kThreads) k_direct_list(const DirectArgs a, const uint32_t *list,
-                                                          const uint32_t *count)
+__global__ void __launch_bounds__(kThreads) k_direct_cells(const DirectArgs a, const CellBlocks cb)
 {
     __shared__ TileSmem<LT> sm;
-    const uint32_t n = *count;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        shoot_tile<K1, K2, T, LT, false, JIT>(a, list[i], i & (kPartials - 1), sm);
+    const uint64_t n = (uint64_t)(*cb.count) * (uint64_t)cb.S;
+    uint32_t it = 0;
+    for (uint64_t base = (uint64_t)blockIdx.x * kThreads; base < n; base += (uint64_t)gridDim.x * kThreads, ++it) {
+        const uint64_t q = base + threadIdx.x;
+        int64_t c0 = 0, r0 = 0, cmax = 0, rmax = 0;
+        if (q < n) {
+            const uint64_t i = q / (uint64_t)cb.S;
+            const int64_t j = (int64_t)(q - i * (uint64_t)cb.S);
+            const int64_t cell = cb.list[i];
+            const int64_t mx = cell % cb.ncx, my = cell / cb.ncx;
+            c0 = mx * cb.c1 + (j % cb.sx) * K1;
+            r0 = my * cb.c2 + (j / cb.sx) * K2;
+            cmax = min((mx + 1) * cb.c1, a.wn1);
+            rmax = min((my + 1) * cb.c2, a.wn2);
+        }
+        shoot_rays<K1, K2, T, LT, false, JIT>(a, c0, r0, cmax, rmax, (blockIdx.x + it) & (kPartials - 1), sm);
         __syncthreads();
     }
 }
@@ -449,40 +476,38 @@ hipError_t launch_k(const DirectArgs &a, int T, int LT, int64_t n_tiles, hipStre
 }
 
 template <int K1, int K2, int T, int LT>
-hipError_t launch_lt(const DirectArgs &a, const uint32_t *list, const uint32_t *count, int64_t max_tiles,
-                     hipStream_t s)
+hipError_t launch_ct(const DirectArgs &a, const CellBlocks &cb, int64_t max_groups, hipStream_t s)
 {
     int occ = 0;
     if (a.jitter) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_list<K1, K2, T, LT, true>, kThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_cells<K1, K2, T, LT, true>, kThreads, 0) !=
             hipSuccess)
             occ = 1;
-    } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_list<K1, K2, T, LT, false>, kThreads,
+    } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_direct_cells<K1, K2, T, LT, false>, kThreads,
                                                             0) != hipSuccess) {
         occ = 1;
     }
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t grid = (int64_t)std::max(1, occ) * std::max(1, cus);
-    if (grid > max_tiles) grid = max_tiles;
+    if (grid > max_groups) grid = max_groups;
     const dim3 g((unsigned)grid), blk(kThreads);
-    if (a.jitter) hipLaunchKernelGGL((k_direct_list<K1, K2, T, LT, true>), g, blk, 0, s, a, list, count);
-    else hipLaunchKernelGGL((k_direct_list<K1, K2, T, LT, false>), g, blk, 0, s, a, list, count);
+    if (a.jitter) hipLaunchKernelGGL((k_direct_cells<K1, K2, T, LT, true>), g, blk, 0, s, a, cb);
+    else hipLaunchKernelGGL((k_direct_cells<K1, K2, T, LT, false>), g, blk, 0, s, a, cb);
     return hipGetLastError();
 }
 
 template <int K1, int K2>
-hipError_t launch_l(const DirectArgs &a, int T, int LT, const uint32_t *list, const uint32_t *count,
-                    int64_t max_tiles, hipStream_t s)
+hipError_t launch_c(const DirectArgs &a, int T, int LT, const CellBlocks &cb, int64_t max_groups, hipStream_t s)
 {
     if (LT == 256) {
-        if (T == 8) return launch_lt<K1, K2, 8, 256>(a, list, count, max_tiles, s);
-        if (T == 16) return launch_lt<K1, K2, 16, 256>(a, list, count, max_tiles, s);
-        if (T == 32) return launch_lt<K1, K2, 32, 256>(a, list, count, max_tiles, s);
+        if (T == 8) return launch_ct<K1, K2, 8, 256>(a, cb, max_groups, s);
+        if (T == 16) return launch_ct<K1, K2, 16, 256>(a, cb, max_groups, s);
+        if (T == 32) return launch_ct<K1, K2, 32, 256>(a, cb, max_groups, s);
     } else if (LT == 512) {
-        if (T == 8) return launch_lt<K1, K2, 8, 512>(a, list, count, max_tiles, s);
-        if (T == 16) return launch_lt<K1, K2, 16, 512>(a, list, count, max_tiles, s);
-        if (T == 32) return launch_lt<K1, K2, 32, 512>(a, list, count, max_tiles, s);
+        if (T == 8) return launch_ct<K1, K2, 8, 512>(a, cb, max_groups, s);
+        if (T == 16) return launch_ct<K1, K2, 16, 512>(a, cb, max_groups, s);
+        if (T == 32) return launch_ct<K1, K2, 32, 512>(a, cb, max_groups, s);
     }
     return hipErrorInvalidValue;
 }
@@ -554,11 +579,11 @@ hipError_t launch_batched(const BatchArgs &b, int K1, int K2, int T, int LT, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_direct_list(const DirectArgs &a, int K1, int K2, int T, int LT, const uint32_t *list,
-                              const uint32_t *count, int64_t max_tiles, hipStream_t s)
+hipError_t launch_direct_cells(const DirectArgs &a, int K1, int K2, int T, int LT, const CellBlocks &cb,
+                               int64_t max_groups, hipStream_t s)
 {
-    if (max_tiles <= 0) return hipSuccess;
-    RS_BLOCK_SWITCH(launch_l, a, T, LT, list, count, max_tiles, s)
+    if (max_groups <= 0) return hipSuccess;
+    RS_BLOCK_SWITCH(launch_c, a, T, LT, cb, max_groups, s)
     return hipErrorInvalidValue;
 }
 

@@ -563,8 +563,8 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
 // ---------------------------------------------------------------- zoom
 
 struct ZoomLayout {
-    int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, tiles = 0;
-    size_t flags_off = 0, list_off = 0, part_off = 0, total = 0;
+    int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, sx = 0, S = 0;
+    size_t list_off = 0, part_off = 0, total = 0;
 };
 
 int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &L)
@@ -577,9 +577,11 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     const double t1 = (g.hi[0] - g.lo[0]) / (double)g.n[0], t2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
     int64_t c1 = z->cell[0], c2 = z->cell[1];
     if (c1 == 0 && c2 == 0) {
-        // about 256 fine rays per cell, square in the image plane
+        // about 256 fine rays per cell, square in the image plane, whole lane blocks
         c1 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(std::sqrt(256.0 * t2 / t1))));
         c2 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(256.0 / (double)c1)));
+        c1 = (c1 + t.K1 - 1) / t.K1 * t.K1;
+        c2 = (c2 + t.K2 - 1) / t.K2 * t.K2;
     } else if (c1 == 0 || c2 == 0) {
         return fail(RS_EINVAL, "zoom cell: give both sizes or neither");
     }
@@ -589,13 +591,13 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     L.ncy = (g.win_n[1] + c2 - 1) / c2;
     L.cells = L.ncx * L.ncy;
     if (L.cells > (int64_t(1) << 30)) return fail(RS_ERANGE, "more than 2^30 culling cells; use larger cells");
-    L.tiles = tile_count(job, t);
-    if (L.tiles >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
+    L.sx = (c1 + t.K1 - 1) / t.K1;
+    L.S = L.sx * ((c2 + t.K2 - 1) / t.K2);
+    if ((uint64_t)L.cells * (uint64_t)L.S * (uint64_t)(t.K1 * t.K2) >= (uint64_t(1) << 40))
+        return fail(RS_ERANGE, "too many ray slots");
     size_t off = 256;
-    L.flags_off = off;
-    off += align256((size_t)L.cells);
     L.list_off = off;
-    off += align256((size_t)L.tiles * sizeof(uint32_t));
+    off += align256((size_t)L.cells * sizeof(uint32_t));
     L.part_off = off;
     off += (size_t)(rs::kPartials * partial_stride(job)) * sizeof(uint32_t);
     L.total = off + 256;
@@ -857,9 +859,12 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     uint32_t *stats = reinterpret_cast<uint32_t *>(base);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // statistics: [0] kept cells (the list length), [1] cells, [2] lane blocks per cell,
+    // [3] rays per lane block
     hipError_t e = rs::launch_fill_u32(stats, 4, 0u, s);
-    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 1, 1, (uint32_t)L.tiles, s);
-    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 3, 1, (uint32_t)std::min<int64_t>(L.cells, 0xffffffffll), s);
+    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 1, 1, (uint32_t)L.cells, s);
+    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 2, 1, (uint32_t)L.S, s);
+    if (e == hipSuccess) e = rs::launch_fill_u32(stats + 3, 1, (uint32_t)(t.K1 * t.K2), s);
     if (e != hipSuccess) return dev_fail(e, "zoom statistics reset");
     const rs_raygrid &g = job->grid;
     if (g.win_n[0] == 0 || g.win_n[1] == 0) return RS_OK;
@@ -884,10 +889,6 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     z.c2 = L.c2;
     z.ncx = L.ncx;
     z.ncy = L.ncy;
-    z.tile_cols = 64 * (int64_t)t.K1;
-    z.tile_rows = (int64_t)rs::kWaves * t.K2;
-    z.tiles_x = (g.win_n[0] + z.tile_cols - 1) / z.tile_cols;
-    z.tiles_y = (g.win_n[1] + z.tile_rows - 1) / z.tile_rows;
     z.lam1 = a.lam1;
     z.lam2 = a.lam2;
     z.zlo1 = job->map.lo[0];
@@ -903,20 +904,90 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     z.xmax = xmax;
     z.vel = a.vel;
     z.time = a.time;
-    z.flags = base + L.flags_off;
     z.list = reinterpret_cast<uint32_t *>(base + L.list_off);
     z.stats = stats;
+
+    rs::CellBlocks cb{};
+    cb.list = z.list;
+    cb.count = stats;
+    cb.c1 = L.c1;
+    cb.c2 = L.c2;
+    cb.ncx = L.ncx;
+    cb.sx = L.sx;
+    cb.S = L.S;
+    const int64_t max_groups = (L.cells * L.S + rs::kThreads - 1) / rs::kThreads;
 
     e = rs::launch_zero(part, rs::kPartials * pstride, s);
     if (e != hipSuccess) return dev_fail(e, "zero partial maps");
     e = rs::launch_zoom_mark(z, s);
     if (e != hipSuccess) return dev_fail(e, "zoom culling launch");
-    e = rs::launch_zoom_tiles(z, s);
-    if (e != hipSuccess) return dev_fail(e, "zoom tile list launch");
-    e = rs::launch_direct_list(a, t.K1, t.K2, t.T, t.LT, z.list, stats, L.tiles, s);
+    e = rs::launch_direct_cells(a, t.K1, t.K2, t.T, t.LT, cb, max_groups, s);
     if (e != hipSuccess) return dev_fail(e, "zoom direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");
+    return RS_OK;
+}
+
+int rs_zoom_stats(const void *workspace, uint64_t out[4], void *stream)
+{
+    g_err[0] = '\0';
+    if (!workspace || !out) return fail(RS_EINVAL, "workspace and out are required");
+    const void *base = reinterpret_cast<const void *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    uint32_t st[4] = {0, 0, 0, 0};
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(st, base, sizeof st, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(e, "zoom statistics read");
+    out[0] = st[0];
+    out[1] = st[1];
+    out[2] = (uint64_t)st[0] * st[2] * st[3];
+    out[3] = (uint64_t)st[1] * st[2] * st[3];
+    return RS_OK;
+}
+
+int rs_plan_grid(const rs_map *map, const rs_macro *macro, double kappa_star, double lens_extent, double n_av,
+                 double margin, rs_raygrid *out, double *n_av_out)
+{
+    g_err[0] = '\0';
+    if (!map || !macro || !out) return fail(RS_EINVAL, "map, macro and out are required");
+    for (int k = 0; k < 2; ++k)
+        if (!is_fin(map->lo[k]) || !is_fin(map->hi[k]) || !(map->hi[k] > map->lo[k]) || map->n[k] <= 0)
+            return fail(RS_EINVAL, "map axis %d invalid", k);
+    if (!is_fin(macro->kappa_c) || !is_fin(macro->gamma)) return fail(RS_EINVAL, "macro not finite");
+    if (!is_fin(kappa_star) || kappa_star < 0.0) return fail(RS_EINVAL, "kappa_star must be finite and >= 0");
+    if (!is_fin(lens_extent) || lens_extent < 0.0) return fail(RS_EINVAL, "lens_extent must be finite and >= 0");
+    if (!is_fin(n_av) || !(n_av > 0.0)) return fail(RS_EINVAL, "n_av must be finite and > 0");
+    if (!is_fin(margin) || margin < 0.0) return fail(RS_EINVAL, "margin must be finite and >= 0");
+    const double f = margin > 0.0 ? margin : 1.2;
+    const double kappa = kappa_star + macro->kappa_c;
+    const double lam[2] = {1.0 - kappa - macro->gamma, 1.0 - kappa + macro->gamma};
+    double half[2], cen[2];
+    for (int k = 0; k < 2; ++k) {
+        const double l = std::fabs(lam[k]) >= 0.05 ? lam[k] : (lam[k] < 0.0 ? -0.05 : 0.05);
+        half[k] = f * 0.5 * (map->hi[k] - map->lo[k]) / std::fabs(l);
+        cen[k] = 0.5 * (map->lo[k] + map->hi[k]) / l;
+    }
+    const double pix = ((map->hi[0] - map->lo[0]) / map->n[0]) * ((map->hi[1] - map->lo[1]) / map->n[1]);
+    const double t0 = std::sqrt(pix / n_av);
+    const double ext = std::max(std::fabs(cen[0]) + half[0], std::fabs(cen[1]) + half[1]) + lens_extent;
+    if (!is_fin(ext) || ext > kMaxCoord) return fail(RS_EINVAL, "planned region too large");
+    const double q = std::ldexp(1.0, std::ilogb(std::max(ext, 1e-30)) - 22);   // 2 ulp32 of ext
+    const double t = std::floor(t0 / q) * q;
+    if (!(t > 0.0)) return fail(RS_ERANGE, "n_av too high: cell below the float32 lattice of the region");
+    for (int k = 0; k < 2; ++k) {
+        const double n = std::ceil(2.0 * half[k] / t);
+        if (n >= 2147483648.0) return fail(RS_ERANGE, "axis %d needs 2^31 rays or more", k);
+        const double c = std::round(cen[k] / t) * t;
+        out->n[k] = (int64_t)n;
+        out->lo[k] = c - 0.5 * n * t;
+        out->hi[k] = c + 0.5 * n * t;
+        out->win_lo[k] = 0;
+        out->win_n[k] = (int64_t)n;
+    }
+    out->jitter_seed = 0;
+    out->jitter = 0;
+    out->reserved = 0;
+    if (n_av_out) *n_av_out = pix / (t * t);
     return RS_OK;
 }
 
@@ -934,16 +1005,6 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
     return e == hipSuccess ? RS_OK : dev_fail(e, "advance lenses launch");
 }
 
-int rs_zoom_stats(const void *workspace, uint32_t out[4], void *stream)
-{
-    g_err[0] = '\0';
-    if (!workspace || !out) return fail(RS_EINVAL, "workspace and out are required");
-    const void *base = reinterpret_cast<const void *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(out, base, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e == hipSuccess ? RS_OK : dev_fail(e, "zoom statistics read");
-}
 
 int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,
                    const double *tracks, int32_t n_tracks, int32_t n_points, double *mu, double *mag,
@@ -962,6 +1023,7 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     if (src->kind != 0 && src->kind != 1) return fail(RS_EINVAL, "source kind must be 0 or 1");
     if (!(src->size > 0.0) || !std::isfinite(src->size)) return fail(RS_EINVAL, "source size must be finite and > 0");
     if (!(src->cutoff >= 0.0) || !std::isfinite(src->cutoff)) return fail(RS_EINVAL, "cutoff must be finite and >= 0");
+    if (src->layout < 0 || src->layout > 2) return fail(RS_EINVAL, "layout must be 0, 1 or 2");
     if (n_tracks == 0) return RS_OK;
     if (!counts || !tracks) return fail(RS_EINVAL, "counts and tracks are required");
     rs::LightArgs a{};
@@ -982,6 +1044,7 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     a.n_points = n_points;
     a.mu = mu;
     a.mag = mag;
+    a.path = src->layout;
     const hipError_t e = rs::launch_light_curve(a, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RS_OK : dev_fail(e, "light-curve launch");
 }

@@ -150,23 +150,28 @@ struct ZoomArgs {
     double glo1, glo2, gt1, gt2;        // fine grid origin and spacing
     int64_t wlo1, wlo2, wn1, wn2;       // fine ray window
     int64_t c1, c2, ncx, ncy;           // fine rays per culling cell, cells per axis
-    int64_t tiles_x, tiles_y, tile_cols, tile_rows;   // fine ray tiles of the direct-sum launch
     double lam1, lam2;
     double zlo1, zlo2, zhi1, zhi2;      // zoom map rectangle
     double margin, pad, xmax;           // caller margin; float32 coordinate allowance; max |x|
     const float2 *vel;                  // lens velocities or null
     double time;
-    uint8_t *flags;                     // ncx * ncy keep flags
-    uint32_t *list;                     // kept tile indices
-    uint32_t *stats;                    // [0] tiles kept (list length), [2] cells kept
+    uint32_t *list;                     // kept cell indices
+    uint32_t *stats;                    // [0] cells kept (list length)
 };
 
 hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s);
 hipError_t launch_advance(const float4 *in, const float2 *vel, int64_t n, double time, float4 *out, hipStream_t s);
-hipError_t launch_zoom_tiles(const ZoomArgs &z, hipStream_t s);
-// Persistent direct sum over the tiles listed in list[0 .. *count).
-hipError_t launch_direct_list(const DirectArgs &a, int K1, int K2, int T, int LT, const uint32_t *list,
-                              const uint32_t *count, int64_t max_tiles, hipStream_t s);
+// Lane blocks (K1 columns x K2 rows) of the culling cells in list[0 .. *count).
+struct CellBlocks {
+    const uint32_t *list;
+    const uint32_t *count;
+    int64_t c1, c2, ncx;    // culling cell size (window columns, rows) and cells per row
+    int64_t sx, S;          // lane blocks per cell row, lane blocks per cell
+};
+
+// Persistent direct sum over the lane blocks of the listed cells.
+hipError_t launch_direct_cells(const DirectArgs &a, int K1, int K2, int T, int LT, const CellBlocks &cb,
+                               int64_t max_groups, hipStream_t s);
 
 // ---------------------------------------------------------------- light curves
 
@@ -182,6 +187,7 @@ struct LightArgs {
     const double *tracks;   // n_tracks x (start1, start2, end1, end2), device
     int32_t n_tracks, n_points;
     double *mu, *mag;       // n_tracks x n_points each (either may be null)
+    int32_t path;           // 0: chosen by size, 1: lane per point, 2: wave per point
 };
 
 hipError_t launch_light_curve(const LightArgs &a, hipStream_t s);

@@ -13,8 +13,8 @@
 // while a lens closer than 3 rho moves the image by at most |alpha_i(x) - alpha_i(c)| <= 2 m_i / delta_i
 // (delta_i = its distance to the cell rectangle); a lens inside the rectangle leaves the image
 // unbounded.  A cell whose bounding box, widened by a rounding allowance, misses the window cannot
-// contribute and is skipped; the fine ray tiles that overlap a kept cell are shot exactly as the
-// plain path shoots them, so the zoom map equals the full fine-grid map on the window.
+// contribute and is skipped; the rays of the kept cells are shot exactly as the plain path shoots
+// them, so the zoom map equals the full fine-grid map on the window.
 #include "rs_internal.h"
 
 namespace rs {
@@ -29,7 +29,7 @@ __device__ __forceinline__ float4 zoom_pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
-// One thread per culling cell.
+// One thread per culling cell; kept cells are appended to the list.
 __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z)
 {
     __shared__ float4 s_lens[2][kZoomLT];
@@ -122,26 +122,7 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z)
     bool keep = inside || !(fabs(y1) < 1e300 && fabs(y2) < 1e300 && E1 < 1e300 && E2 < 1e300);
     if (!keep)
         keep = (y1 + E1 >= z.zlo1) && (y1 - E1 <= z.zhi1) && (y2 + E2 >= z.zlo2) && (y2 - E2 <= z.zhi2);
-    z.flags[cell] = keep ? 1 : 0;
-    if (keep) atomicAdd(&z.stats[2], 1u);
-}
-
-// One thread per fine ray tile: append the tile if any culling cell it overlaps is kept.
-__global__ void __launch_bounds__(256) k_zoom_tiles(const ZoomArgs z)
-{
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= z.tiles_x * z.tiles_y) return;
-    const int64_t tx = t % z.tiles_x, ty = t / z.tiles_x;
-    const int64_t c_lo = tx * z.tile_cols, c_hi = min((tx + 1) * z.tile_cols, z.wn1);
-    const int64_t r_lo = ty * z.tile_rows, r_hi = min((ty + 1) * z.tile_rows, z.wn2);
-    bool keep = false;
-    for (int64_t my = r_lo / z.c2; my <= (r_hi - 1) / z.c2 && !keep; ++my)
-        for (int64_t mx = c_lo / z.c1; mx <= (c_hi - 1) / z.c1; ++mx)
-            if (z.flags[my * z.ncx + mx]) {
-                keep = true;
-                break;
-            }
-    if (keep) z.list[atomicAdd(&z.stats[0], 1u)] = (uint32_t)t;
+    if (keep) z.list[atomicAdd(&z.stats[0], 1u)] = (uint32_t)cell;
 }
 
 }  // namespace
@@ -151,14 +132,6 @@ hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s)
     const int64_t cells = z.ncx * z.ncy;
     if (cells <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((cells + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z);
-    return hipGetLastError();
-}
-
-hipError_t launch_zoom_tiles(const ZoomArgs &z, hipStream_t s)
-{
-    const int64_t n = z.tiles_x * z.tiles_y;
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zoom_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z);
     return hipGetLastError();
 }
 

@@ -17,6 +17,15 @@ pytestmark = pytest.mark.gpu
 
 MU_RTOL = 1e-12
 MAG_ATOL = 1e-11
+LAYOUT = {"v": 0}
+
+
+@pytest.fixture(params=["lanes", "waves"], autouse=True)
+def layout(request):
+    # every test runs on both evaluation layouts of the kernel
+    LAYOUT["v"] = request.param
+    yield request.param
+    LAYOUT["v"] = 0
 
 
 def _env():
@@ -33,7 +42,7 @@ def _gpu(counts, lo, hi, n, n_av, tracks, n_points, kind, size, cutoff=0.0):
     dev = torch.device("cuda:0")
     c = torch.from_numpy(np.ascontiguousarray(counts).view(np.int32)).to(dev)
     t = torch.from_numpy(np.ascontiguousarray(tracks, dtype=np.float64)).to(dev)
-    mu, mag = P.light_curve(c, lo, hi, n, n_av, t, n_points, kind, size, cutoff)
+    mu, mag = P.light_curve(c, lo, hi, n, n_av, t, n_points, kind, size, cutoff, layout=LAYOUT["v"])
     torch.cuda.synchronize()
     return mu.cpu().numpy(), mag.cpu().numpy()
 
@@ -44,7 +53,10 @@ def _compare(mu_g, mag_g, mu_o, mag_o, exact):
     if exact:
         assert np.array_equal(mu_g[ok], mu_o[ok])
     else:
-        rel = np.abs(mu_g[ok] - mu_o[ok]) / np.abs(mu_o[ok])
+        zero = ok & (mu_o == 0)
+        assert np.all(mu_g[zero] == 0)             # every pixel in the support is empty
+        nz = ok & (mu_o != 0)
+        rel = np.abs(mu_g[nz] - mu_o[nz]) / np.abs(mu_o[nz])
         assert np.all(rel <= MU_RTOL), rel.max()
     fin = ok & (mu_o > 0)
     assert np.all(np.abs(mag_g[fin] - mag_o[fin]) <= MAG_ATOL)
@@ -67,8 +79,9 @@ def test_disc_bit_exact_on_seeded_map(radius):
     _compare(mu_g, mag_g, mu_o, mag_o, exact=True)
 
 
-# the last case's support box is wider than the kernel's LDS staging (per-pixel path)
-@pytest.mark.parametrize("sigma,cutoff", [(0.11, 0.0), (0.04, 6.0), (0.9, 3.0), (2.0, 4.0)])
+# (2.0, 4.0): support box wider than the wave layout's LDS staging (per-pixel path);
+# (0.002, 30.0): a source far narrower than a pixel (the lane layout's direct-exp path)
+@pytest.mark.parametrize("sigma,cutoff", [(0.11, 0.0), (0.04, 6.0), (0.9, 3.0), (2.0, 4.0), (0.002, 30.0)])
 def test_gaussian_parity_on_seeded_map(sigma, cutoff):
     counts = synth.count_map(23, N, 40.0)
     tr = synth.light_tracks(24, 10, LO, HI, 7.0)
@@ -146,7 +159,7 @@ def test_shoot_then_light_curve_chain():
     nav = oracle.n_av(w)
     tr = synth.light_tracks(30, 6, w.map_lo, w.map_hi, 15.0)
     t = torch.from_numpy(tr).to(dev)
-    mu, _ = P.light_curve(counts, w.map_lo, w.map_hi, w.map_n, nav, t, 101, "gaussian", 0.25)
+    mu, _ = P.light_curve(counts, w.map_lo, w.map_hi, w.map_n, nav, t, 101, "gaussian", 0.25, layout=LAYOUT["v"])
     torch.cuda.synchronize()
     mu_g = mu.cpu().numpy()
     cg = counts.cpu().numpy().view(np.uint32).astype(np.int64)

@@ -124,7 +124,7 @@ def test_zoom_on_moving_field_equals_fine_grid():
             ws = torch.empty(P.zoom_workspace_bytes(job, z), dtype=torch.uint8, device=dev)
             P.shoot_zoom(job, z, ws)
             st = P.zoom_stats(ws)
-            assert st["tiles_shot"] < st["tiles"]
+            assert st["slots_shot"] < st["slots"]
         else:
             ws = torch.empty(P.workspace_bytes(job), dtype=torch.uint8, device=dev)
             P.shoot_job(job, ws)

@@ -57,7 +57,7 @@ def test_zoom_equals_fine_grid_small_field():
     cp, cz, st = _run(w, _fine(w, 3), (-2.0, 0.5), (1.0, 3.5), (150, 150))
     print("small field zoom:", st, "counts", int(cp.sum()))
     assert cp.sum() > 0 and np.array_equal(cp, cz)
-    assert st["tiles_shot"] < st["tiles"] and st["cells_kept"] < st["cells"]
+    assert st["slots_shot"] < 0.5 * st["slots"] and st["cells_kept"] < st["cells"]
 
 
 def test_zoom_against_oracle_fine_map():
@@ -84,7 +84,7 @@ def test_zoom_equals_fine_grid_paper_field(block, jitter):
     cp, cz, st = _run(w, w.grid_n, (-1.25, -1.25), (1.25, 1.25), (256, 256), opts=o, jitter_seed=jitter)
     print("paper field zoom:", block, jitter, st, "counts", int(cp.sum()))
     assert cp.sum() > 0 and np.array_equal(cp, cz)
-    assert st["tiles_shot"] < 0.25 * st["tiles"]
+    assert st["cells_kept"] < 0.15 * st["cells"] and st["slots_shot"] < 0.15 * st["slots"]
 
 
 def test_zoom_window_cells_and_margin():
@@ -96,7 +96,7 @@ def test_zoom_window_cells_and_margin():
         cp, cz, st = _run(w, w.grid_n, (0.5, -3.0), (3.0, -0.5), (200, 200), window=win,
                           zoom=P.zoom_params(cell, margin))
         assert np.array_equal(cp, cz), (cell, margin)
-        assert st["cells"] == -(-2500 // cell[0]) * -(-3001 // cell[1])
+        assert st["cells"] == -(-2500 // cell[0]) * -(-3001 // cell[1]) and st["slots_shot"] < st["slots"]
 
 
 def test_zoom_far_from_every_ray_and_empty_window():
@@ -104,6 +104,6 @@ def test_zoom_far_from_every_ray_and_empty_window():
     w = synth.workload_small()
     cp, cz, st = _run(w, w.grid_n, (500.0, 500.0), (501.0, 501.0), (10, 10))
     assert cp.sum() == 0 and cz.sum() == 0
-    assert st["tiles_shot"] <= st["tiles"] // 4
+    assert st["slots_shot"] <= st["slots"] // 4
     cp, cz, st = _run(w, w.grid_n, (-1.0, -1.0), (1.0, 1.0), (10, 10), window=((5, 5), (0, 7)))
-    assert cz.sum() == 0 and st["tiles_shot"] == 0
+    assert cz.sum() == 0 and st["slots_shot"] == 0

@@ -564,7 +564,8 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
 
 struct ZoomLayout {
     int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, sx = 0, S = 0;
-    size_t list_off = 0, part_off = 0, total = 0;
+    int64_t P = 4, npx = 0, npy = 0;     // culling cells per parent side, parents per axis
+    size_t parent_off = 0, list_off = 0, part_off = 0, total = 0;
 };
 
 int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &L)
@@ -595,7 +596,11 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     L.S = L.sx * ((c2 + t.K2 - 1) / t.K2);
     if ((uint64_t)L.cells * (uint64_t)L.S * (uint64_t)(t.K1 * t.K2) >= (uint64_t(1) << 40))
         return fail(RS_ERANGE, "too many ray slots");
+    L.npx = (L.ncx + L.P - 1) / L.P;
+    L.npy = (L.ncy + L.P - 1) / L.P;
     size_t off = 256;
+    L.parent_off = off;
+    off += align256((size_t)(L.npx * L.npy) * sizeof(uint32_t));
     L.list_off = off;
     off += align256((size_t)L.cells * sizeof(uint32_t));
     L.part_off = off;
@@ -860,8 +865,8 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     uint32_t *stats = reinterpret_cast<uint32_t *>(base);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // statistics: [0] kept cells (the list length), [1] cells, [2] lane blocks per cell,
-    // [3] rays per lane block
-    hipError_t e = rs::launch_fill_u32(stats, 4, 0u, s);
+    // [3] rays per lane block, [4] kept parents
+    hipError_t e = rs::launch_fill_u32(stats, 8, 0u, s);
     if (e == hipSuccess) e = rs::launch_fill_u32(stats + 1, 1, (uint32_t)L.cells, s);
     if (e == hipSuccess) e = rs::launch_fill_u32(stats + 2, 1, (uint32_t)L.S, s);
     if (e == hipSuccess) e = rs::launch_fill_u32(stats + 3, 1, (uint32_t)(t.K1 * t.K2), s);
@@ -904,6 +909,12 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     z.xmax = xmax;
     z.vel = a.vel;
     z.time = a.time;
+    z.P = L.P;
+    z.npx = L.npx;
+    z.npy = L.npy;
+    z.parents_out = reinterpret_cast<uint32_t *>(base + L.parent_off);
+    z.parents = z.parents_out;
+    z.n_parents = stats + 4;
     z.list = reinterpret_cast<uint32_t *>(base + L.list_off);
     z.stats = stats;
 

@@ -150,13 +150,17 @@ struct ZoomArgs {
     double glo1, glo2, gt1, gt2;        // fine grid origin and spacing
     int64_t wlo1, wlo2, wn1, wn2;       // fine ray window
     int64_t c1, c2, ncx, ncy;           // fine rays per culling cell, cells per axis
+    int64_t P, npx, npy;                // culling cells per parent side; parents per axis
     double lam1, lam2;
     double zlo1, zlo2, zhi1, zhi2;      // zoom map rectangle
     double margin, pad, xmax;           // caller margin; float32 coordinate allowance; max |x|
     const float2 *vel;                  // lens velocities or null
     double time;
+    uint32_t *parents_out;              // kept parent indices (level 0 output)
+    const uint32_t *parents;            // the same list, read by level 1
+    const uint32_t *n_parents;          // its length (stats + 4)
     uint32_t *list;                     // kept cell indices
-    uint32_t *stats;                    // [0] cells kept (list length)
+    uint32_t *stats;                    // [0] cells kept (list length), [4] parents kept
 };
 
 hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s);

@@ -29,16 +29,41 @@ __device__ __forceinline__ float4 zoom_pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
-// One thread per culling cell; kept cells are appended to the list.
-__global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z)
+// One thread per cell of one culling level; kept cells are appended to `out`.
+//   level 0: the parent cells, P x P culling cells each, all of them;
+//   level 1: the culling cells inside the kept parents: thread t takes child t % P^2 of
+//            parent parents[t / P^2].
+__global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int level)
 {
     __shared__ float4 s_lens[2][kZoomLT];
-    const int64_t cell = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool active = cell < z.ncx * z.ncy;
-    const int64_t mx = active ? cell % z.ncx : 0, my = active ? cell / z.ncx : 0;
+    const int64_t t_id = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t P = z.P, PP = z.P * z.P;
+    int64_t n_items, cx = 0, cy = 0, cw1, cw2, idx = 0;
+    if (level == 0) {
+        n_items = z.npx * z.npy;
+        if (t_id < n_items) {
+            cx = t_id % z.npx;
+            cy = t_id / z.npx;
+            idx = t_id;
+        }
+        cw1 = P * z.c1;
+        cw2 = P * z.c2;
+    } else {
+        n_items = (int64_t)(*z.n_parents) * PP;
+        if (t_id < n_items) {
+            const int64_t par = z.parents[t_id / PP], k = t_id % PP;
+            cx = (par % z.npx) * P + k % P;
+            cy = (par / z.npx) * P + k / P;
+            idx = cy * z.ncx + cx;
+        }
+        cw1 = z.c1;
+        cw2 = z.c2;
+    }
+    if ((int64_t)blockIdx.x * kThreads >= n_items) return;      // whole workgroup idle
+    const bool active = t_id < n_items && cx * cw1 < z.wn1 && cy * cw2 < z.wn2;
     // fine-grid index range of the cell (global indices), its rectangle, centre and half-widths
-    const int64_t g10 = z.wlo1 + mx * z.c1, g11 = z.wlo1 + min((mx + 1) * z.c1, z.wn1);
-    const int64_t g20 = z.wlo2 + my * z.c2, g21 = z.wlo2 + min((my + 1) * z.c2, z.wn2);
+    const int64_t g10 = z.wlo1 + min(cx * cw1, z.wn1), g11 = z.wlo1 + min((cx + 1) * cw1, z.wn1);
+    const int64_t g20 = z.wlo2 + min(cy * cw2, z.wn2), g21 = z.wlo2 + min((cy + 1) * cw2, z.wn2);
     const double e1lo = z.glo1 + (double)g10 * z.gt1, e1hi = z.glo1 + (double)g11 * z.gt1;
     const double e2lo = z.glo2 + (double)g20 * z.gt2, e2hi = z.glo2 + (double)g21 * z.gt2;
     const float cf1 = (float)(0.5 * (e1lo + e1hi)), cf2 = (float)(0.5 * (e2lo + e2hi));
@@ -122,16 +147,26 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z)
     bool keep = inside || !(fabs(y1) < 1e300 && fabs(y2) < 1e300 && E1 < 1e300 && E2 < 1e300);
     if (!keep)
         keep = (y1 + E1 >= z.zlo1) && (y1 - E1 <= z.zhi1) && (y2 + E2 >= z.zlo2) && (y2 - E2 <= z.zhi2);
-    if (keep) z.list[atomicAdd(&z.stats[0], 1u)] = (uint32_t)cell;
+    if (keep) {
+        uint32_t *out = level == 0 ? z.parents_out : z.list;
+        uint32_t *cnt = level == 0 ? &z.stats[4] : &z.stats[0];
+        out[atomicAdd(cnt, 1u)] = (uint32_t)idx;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s)
 {
-    const int64_t cells = z.ncx * z.ncy;
-    if (cells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((cells + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z);
+    const int64_t parents = z.npx * z.npy;
+    if (parents <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((parents + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // level 1 over at most every child of every parent; workgroups past the kept children exit
+    const int64_t children = parents * z.P * z.P;
+    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((children + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z,
+                       1);
     return hipGetLastError();
 }
 

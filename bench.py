@@ -288,6 +288,28 @@ def bench_surrogate(args, which=None, emit=True):
 
     plain_s = timed(plain)
     m_pl = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+    moving = None
+    if not large:
+        # the same closure reused across frames of a moving field (velocity dispersion 0.05 per
+        # axis): each frame refreshes the far set's affine base and moves the near lenses; the
+        # last frame is judged by the plain direct sum of the moved field
+        vel = torch.from_numpy(synth.lens_velocities(24, w.n_lens, 0.05)).to(dev)
+        frame_s, times = [], [1.0, 2.0, 4.0]
+        for t_f in times:
+            mj = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
+                            w.map_n, counts, lost, velocities=vel, time=t_f)
+            counts.zero_()
+            lost.zero_()
+            frame_s.append(timed(lambda: P.farfield_eval(mj, cfg, model, ews)))
+        m_mov = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+        counts.zero_()
+        lost.zero_()
+        mov_plain_s = timed(lambda: P.shoot_job(mj, pws, None, stream))
+        m_mpl = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+        moving = {"sigma_v": 0.05, "times": times, "frame_s": frame_s,
+                  "plain_frame_s": mov_plain_s, "speedup_vs_plain_per_frame": mov_plain_s / float(np.mean(frame_s)),
+                  "map_l1_rel_err_last_frame": float(np.abs(m_mov - m_mpl).sum() / max(1, m_mpl.sum())),
+                  "frozen_closure_l1_last_frame": float(np.abs(m_sur - m_mpl).sum() / max(1, m_mpl.sum()))}
     l1 = float(np.abs(m_sur - m_pl).sum() / max(1, m_pl.sum()))
     l1_aff = float(np.abs(m_aff - m_pl).sum() / max(1, m_pl.sum()))
     plain_rays_s = judge_rays / plain_s
@@ -307,6 +329,8 @@ def bench_surrogate(args, which=None, emit=True):
         "break_even_rays_per_tile": fit_s * plain_rays_s / n_tiles,
         "map_l1_rel_err": {"surrogate": l1, "affine_only": l1_aff, "tolerance": 0.01},
     }
+    if moving is not None:
+        out["moving_frames"] = moving
     if l1 > 0.01:
         print(f"bench.py: surrogate map error {l1:.3e} above the 1% tolerance", file=sys.stderr)
         sys.exit(3)
@@ -543,6 +567,8 @@ def main():
             out[f"surrogate_{which}"] = {k: r[k] for k in ("config", "fit_s", "eval_s", "plain_s_on_judged_tiles",
                                                             "rays_per_s", "speedup_vs_plain",
                                                             "break_even_rays_per_tile", "map_l1_rel_err")}
+            if "moving_frames" in r:
+                out[f"surrogate_{which}"]["moving_frames"] = r["moving_frames"]
     if not args.no_cpu_baseline:
         print("bench.py: CPU oracle baseline next", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -120,7 +120,8 @@ typedef struct {
      * (v1, v2) float32, or NULL for a static field.  The job then shoots the field at `time`:
      * lens i sits at float32((double)x_i + (double)v_i * time) per axis (FP64, then rounded),
      * its mass unchanged.  rs_shoot, rs_shoot_batched and rs_shoot_zoom apply it while staging
-     * lenses; the far-field entry points reject it (materialise with rs_advance_lenses). */
+     * lenses; rs_farfield_fit rejects it and rs_farfield_eval evaluates a fitted closure at
+     * `time` (see there). */
     const float *velocities;
     double time;
 } rs_job;
@@ -254,6 +255,10 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
  * cfg->eval_tiles only the listed tiles are shot (e.g. a seeded subset judged against
  * rs_shoot on the same tile windows).  Reads the model header and the tile list first
  * (synchronises the stream); RS_ENOTFIT on a model mismatch, RS_EINVAL on a bad tile index.
+ * Moving field (section 5, one closure reused across frames): with job->velocities the job's
+ * lens positions are those of the fit; each tile's near set is still chosen by them, its
+ * lenses enter at their positions at job->time; the far set's affine base alpha_far(c),
+ * J_far(c) is recomputed in FP64 at job->time, and the fitted network residual is kept.
  */
 int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *model, size_t model_bytes,
                      void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);

@@ -175,10 +175,14 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 
 // ---------------------------------------------------------------- fit: affine base
 
+// One workgroup per tile: alpha_far(c) and its Jacobian over the far set, FP64.  At fit time
+// the result goes into the model's tile header.  For a moving field (eval with velocities) the
+// far set is still the one chosen by the fit-time positions, each far lens enters at its
+// position at f.time, and the result goes to f.affine (only the evaluated tiles).
 __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 {
     __shared__ double red[4][256];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = (f.affine && f.eval_tiles) ? (uint32_t)f.eval_tiles[blockIdx.x] : blockIdx.x;
     double lo[2], hi[2], c[2], hw[2];
     int64_t i0[2];
     int n[2];
@@ -186,8 +190,9 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
     const double rn2 = f.r_near * f.r_near;
     double a1 = 0, a2 = 0, j11 = 0, j12 = 0;
     for (int64_t i = threadIdx.x; i < f.n_lens; i += 256) {
-        const float4 l = f.lenses[i];
-        if (is_near(l.x, l.y, lo, hi, rn2)) continue;
+        const float4 l0 = f.lenses[i];
+        if (is_near(l0.x, l0.y, lo, hi, rn2)) continue;
+        const float4 l = moved_lens(l0, f.vel, i, f.time);
         const double dx = c[0] - (double)l.x, dy = c[1] - (double)l.y, m = l.z;
         const double r2 = dx * dx + dy * dy;
         const double q = m / r2, q2 = q / r2;
@@ -206,7 +211,14 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
             for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && f.affine) {
+        double *o = f.affine + 8 * (size_t)tile;
+        o[0] = red[0][0];
+        o[1] = red[1][0];
+        o[2] = red[2][0];
+        o[3] = red[3][0];
+        o[4] = -red[2][0];
+    } else if (threadIdx.x == 0) {
         double *h = tile_hdr(f, tile);
         h[0] = c[0];
         h[1] = c[1];
@@ -614,7 +626,9 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     int n[2];
     tile_geom(f, tile, lo, hi, c, hw, i0, n);
     const double *hd = tile_hdr(f, tile);
-    const double a01 = hd[4], a02 = hd[5], j11 = hd[6], j12 = hd[7], j22 = hd[8], st = hd[9];
+    // a moving field uses the affine base refreshed at f.time; the network residual is the fitted one
+    const double *ab = f.affine ? f.affine + 8 * (size_t)tile : hd + 4;
+    const double a01 = ab[0], a02 = ab[1], j11 = ab[2], j12 = ab[3], j22 = ab[4], st = hd[9];
     const uint16_t *wsrc = tile_w(f, tile);
     const float *bsrc = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(wsrc) + kTileBiasOff);
     for (int p = tid; p < kNParams; p += 256) Wbf[p] = wsrc[p];
@@ -652,8 +666,10 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
                     const int row = (cy0 + r) * g.ncx;
                     const int len = g.start[row + cx1 + 1] - g.start[row + cx0];
                     if (e < len) {
-                        const float4 l = g.lenses[g.idx[g.start[row + cx0] + e]];
-                        if (is_near(l.x, l.y, lo, hi, rn2)) v = l;
+                        // near set by fit-time position; a moving lens enters at its position at f.time
+                        const int li = g.idx[g.start[row + cx0] + e];
+                        const float4 l = g.lenses[li];
+                        if (is_near(l.x, l.y, lo, hi, rn2)) v = moved_lens(l, f.vel, li, f.time);
                         break;
                     }
                     e -= len;
@@ -793,6 +809,10 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint32_t grid = (uint32_t)(f.eval_tiles ? f.n_eval : f.n_tiles);
     if (grid == 0) return hipSuccess;
+    if (f.affine) {
+        hipLaunchKernelGGL(k_ff_affine, dim3(grid), dim3(256), 0, s, f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (f.ray_y)
         hipLaunchKernelGGL((k_surrogate<true>), dim3(grid), dim3(256), 0, s, f, g);
     else

@@ -382,12 +382,13 @@ struct FarGeom {
     double cs;
 };
 
-int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g)
+int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g, bool eval = false)
 {
     int st = validate_job(job);
     if (st != RS_OK) return st;
     if (!c) return fail(RS_EINVAL, "far-field config is NULL");
-    if (job->velocities) return fail(RS_EINVAL, "far-field jobs take a static field (materialise moving lenses with rs_advance_lenses)");
+    if (job->velocities && !eval)
+        return fail(RS_EINVAL, "the far-field fit takes a static field (velocities apply to rs_farfield_eval)");
     if (c->tile_rays[0] <= 0 || c->tile_rays[1] <= 0) return fail(RS_EINVAL, "tile_rays must be > 0");
     if (!(c->r_near > 0.0) || !std::isfinite(c->r_near)) return fail(RS_EINVAL, "r_near must be finite and > 0");
     if (c->n_samples <= 0 || c->n_samples % 1024) return fail(RS_EINVAL, "n_samples must be a positive multiple of 1024");
@@ -496,7 +497,8 @@ size_t eval_ws_bytes(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
     int64_t ncx, ncy;
     cell_geom(job, c, g, ox, oy, ncx, ncy);
     const size_t cells = (size_t)(ncx * ncy);
-    return align256(cells * 4) * 2 + align256((cells + 1) * 4) + align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4) + 256;
+    return align256(cells * 4) * 2 + align256((cells + 1) * 4) + align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4) +
+           align256((size_t)g.n_tiles * 8 * sizeof(double)) + 256;
 }
 
 }  // namespace
@@ -724,7 +726,7 @@ int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, siz
 size_t rs_farfield_model_bytes(const rs_job *job, const rs_ff_config *cfg)
 {
     FarGeom g;
-    if (validate_ff(job, cfg, g) != RS_OK) return 0;
+    if (validate_ff(job, cfg, g, true) != RS_OK) return 0;
     return rs::kModelHeader + (size_t)g.n_tiles * rs::kTileRecord;
 }
 
@@ -738,7 +740,7 @@ size_t rs_farfield_fit_workspace_bytes(const rs_job *job, const rs_ff_config *cf
 size_t rs_farfield_eval_workspace_bytes(const rs_job *job, const rs_ff_config *cfg)
 {
     FarGeom g;
-    if (validate_ff(job, cfg, g) != RS_OK) return 0;
+    if (validate_ff(job, cfg, g, true) != RS_OK) return 0;
     double ox, oy;
     int64_t ncx, ncy;
     cell_geom(job, cfg, g, ox, oy, ncx, ncy);
@@ -775,7 +777,7 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
 {
     g_err[0] = '\0';
     FarGeom g;
-    int st = validate_ff(job, cfg, g);
+    int st = validate_ff(job, cfg, g, true);
     if (st != RS_OK) return st;
     if (!model || !workspace) return fail(RS_EINVAL, "model and workspace are required");
     if (opts && ((opts->ray_y == nullptr) != (opts->ray_pix == nullptr)))
@@ -832,6 +834,12 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     cg.cursor = reinterpret_cast<int32_t *>(base + align256(cells * 4));
     cg.start = reinterpret_cast<int32_t *>(base + 2 * align256(cells * 4));
     cg.idx = reinterpret_cast<int32_t *>(base + 2 * align256(cells * 4) + align256((cells + 1) * 4));
+    if (job->velocities) {
+        f.vel = reinterpret_cast<const float2 *>(job->velocities);
+        f.time = job->time;
+        f.affine = reinterpret_cast<double *>(base + 2 * align256(cells * 4) + align256((cells + 1) * 4) +
+                                              align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4));
+    }
     e = rs::launch_zero(reinterpret_cast<uint32_t *>(base), (int64_t)(2 * align256(cells * 4) / 4), s);
     if (e == hipSuccess) e = rs::launch_ff_eval(f, cg, s);
     return e == hipSuccess ? RS_OK : dev_fail(e, "far-field eval launch");

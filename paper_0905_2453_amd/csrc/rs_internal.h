@@ -124,6 +124,9 @@ struct FarArgs {
     int32_t *ray_pix;
     int32_t affine_only;
     const int32_t *eval_tiles;    // optional tile list (blockIdx.x -> tile)
+    const float2 *vel;            // moving field (eval only): lens velocities, or null
+    double time;
+    double *affine;               // moving field: refreshed affine bases, n_tiles x 8 doubles
     int64_t n_eval;
     int64_t gn1;                  // full grid width, jitter keys and switch (as DirectArgs)
     uint64_t jkey1, jkey2;

@@ -314,9 +314,11 @@ def test_moving_lens_validation_without_device():
     assert L.rs_workspace_bytes(ctypes.byref(j), None) == 0
     j.time = 2.0
     assert L.rs_workspace_bytes(ctypes.byref(j), None) > 0
-    # the far-field closure takes a static field only
+    # the closure is fitted on a static field; evaluating it on a moving one is allowed
     c = _ffcfg()
-    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0
+    assert L.rs_farfield_fit_workspace_bytes(ctypes.byref(j), ctypes.byref(c)) == 0
+    assert L.rs_farfield_eval_workspace_bytes(ctypes.byref(j), ctypes.byref(c)) > 0
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) > 0
     assert L.rs_advance_lenses(None, None, 5, 1.0, None, None) == -1
     assert L.rs_advance_lenses(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 5, float("inf"),
                                ctypes.c_void_p(0x3000), None) == -1

@@ -9,6 +9,7 @@ density; the affine base alone (network off) must fail that bound.
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from oracle import farfield as off
 from oracle import mlp
@@ -189,3 +190,102 @@ def test_mismatched_model_is_rejected():
     with pytest.raises(P.RayShootError) as ei:
         P.farfield_eval(job, cfg, model, ews)
     assert ei.value.status == -5
+
+
+# ---------------------------------------------------------------- moving field, one closure
+
+def _eval(torch, P, job, cfg, model, counts, lost, flags=0, dump=False):
+    dev = torch.device("cuda:0")
+    counts.zero_()
+    lost.zero_()
+    ews = torch.empty(P.farfield_eval_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    o = P.Opts()
+    o.flags = flags
+    nr = job.grid.win_n[0] * job.grid.win_n[1]
+    ry = rp = None
+    if dump:
+        ry = torch.full((nr, 2), float("nan"), dtype=torch.float64, device=dev)
+        rp = torch.full((nr,), -7, dtype=torch.int32, device=dev)
+        o.ray_y, o.ray_pix = ry.data_ptr(), rp.data_ptr()
+    P.farfield_eval(job, cfg, model, ews, o)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+    return (c, ry.cpu().numpy(), rp.cpu().numpy()) if dump else c
+
+
+def _moving_job(P, job, w, lenses, counts, lost, vel, t):
+    return P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                      counts, lost, window=((job.grid.win_lo[0], job.grid.win_lo[1]),
+                                            (job.grid.win_n[0], job.grid.win_n[1])), velocities=vel, time=t)
+
+
+def test_moving_eval_at_time_zero_equals_static():
+    torch, P = _env()
+    w = _small_field()
+    job, cfg, model, dg, dt, u, p0, keep = _fit(torch, P, w, WIN, steps=20)
+    lenses, counts, lost = keep[0], keep[1], keep[2]
+    vel = torch.from_numpy(synth.lens_velocities(21, w.n_lens, 0.3)).to("cuda:0")
+    c_static = _eval(torch, P, job, cfg, model, counts, lost)
+    c_t0 = _eval(torch, P, _moving_job(P, job, w, lenses, counts, lost, vel, 0.0), cfg, model, counts, lost)
+    assert c_static.sum() > 0 and np.array_equal(c_static, c_t0)
+
+
+def test_moving_eval_affine_and_near_field_match_oracle():
+    # network off: y = lambda x - (affine base of the far set at time t + near set at time t),
+    # near and far sets chosen by the fit-time positions
+    torch, P = _env()
+    w = _small_field()
+    job, cfg, model, dg, dt, u, p0, keep = _fit(torch, P, w, WIN, steps=1)
+    lenses, counts, lost = keep[0], keep[1], keep[2]
+    v = synth.lens_velocities(22, w.n_lens, 0.3)
+    t = 1.5
+    vel = torch.from_numpy(v).to("cuda:0")          # the job holds only its address: keep it alive
+    mj = _moving_job(P, job, w, lenses, counts, lost, vel, t)
+    _, ry, _ = _eval(torch, P, mj, cfg, model, counts, lost, flags=P._abi.RS_FLAG_AFFINE_ONLY, dump=True)
+    Lt = oracle.lenses_at(w.lenses, v, t)
+    lam = (1.0 - w.gamma - w.kappa_c, 1.0 + w.gamma - w.kappa_c)
+    (wl1, wl2), (wn1, wn2) = WIN
+    for tile in (0, 5):
+        tx, ty = tile % 4, tile // 4
+        lo, hi, c, h, (i0, n) = off.tile_rect(w, WIN, TILE, tx, ty)
+        near = off.near_mask(w.lenses, lo, hi, R_NEAR)
+        a0, J = off.affine_base(np.ascontiguousarray(Lt[~near]), c)
+        idx = synth.sample_indices(23 + tile, n[0] * n[1], 400)
+        ix, iy = idx % n[0], idx // n[0]
+        g1, g2 = i0[0] + ix, i0[1] + iy
+        x = np.stack([oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0])[g1],
+                      oracle.axis(w.grid_lo[1], w.grid_hi[1], w.grid_n[1])[g2]], 1).astype(np.float64)
+        Ln = np.ascontiguousarray(Lt[near])
+        an = oracle.deflect(Ln, x)
+        y_o = np.stack([lam[0] * x[:, 0], lam[1] * x[:, 1]], 1) - (a0[None, :] + (x - c[None, :]) @ J.T + an)
+        rw = (g2 - wl2) * wn1 + (g1 - wl1)
+        s = np.sum(Ln[None, :, 2] / np.hypot(x[:, None, 0] - Ln[None, :, 0], x[:, None, 1] - Ln[None, :, 1]), 1)
+        bound = 48 * 2.0 ** -24 * s[:, None] + 1e-9 * (1 + np.abs(y_o))
+        assert np.all(np.abs(ry[rw] - y_o) <= bound), np.max(np.abs(ry[rw] - y_o) / bound)
+
+
+def test_moving_surrogate_error_vs_plain_moving_field():
+    # the 1e6-lens closure workload's field and tiles on a 1024 x 512-ray window (128 tiles),
+    # fitted once at time 0 and evaluated at time 2 with a velocity dispersion of 0.05 per axis
+    # (0.1 Einstein radii RMS displacement); the plain direct sum of the moved field judges it
+    torch, P = _env()
+    w = synth.workload_farfield()
+    win = ((3584, 3840), (1024, 512))
+    job, cfg, model, dg, dt, u, p0, keep = _fit(torch, P, w, win, steps=2000)
+    lenses, counts, lost = keep[0], keep[1], keep[2]
+    dev = torch.device("cuda:0")
+    vel = torch.from_numpy(synth.lens_velocities(24, w.n_lens, 0.05)).to(dev)
+    t = 2.0
+    mj = _moving_job(P, job, w, lenses, counts, lost, vel, t)
+    c_mov = _eval(torch, P, mj, cfg, model, counts, lost)
+    c_frozen = _eval(torch, P, job, cfg, model, counts, lost)        # the closure ignoring the motion
+    counts.zero_()
+    lost.zero_()
+    ws = torch.empty(P.workspace_bytes(mj), dtype=torch.uint8, device=dev)
+    P.shoot_job(mj, ws)
+    torch.cuda.synchronize()
+    c_pl = counts.cpu().numpy().view(np.uint32).astype(np.int64)
+    l1 = np.abs(c_mov - c_pl).sum() / c_pl.sum()
+    l1_frozen = np.abs(c_frozen - c_pl).sum() / c_pl.sum()
+    print(f"moving field at t={t}: closure map L1 {l1:.2e}, frozen closure {l1_frozen:.2e}")
+    assert l1 <= 1e-2 and l1_frozen > 3 * l1

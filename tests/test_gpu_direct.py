@@ -254,6 +254,12 @@ def test_paper_scale_sampled_parity():
     assert est <= SWITCH_TOL
     assert abs(slope) < 1.5e-9
     assert nd <= 4
+    # the whole map: mean N / N_av over the 20 x 20 source region is the field's mean
+    # magnification 1 / |(1 - kappa)^2 - gamma^2| = 10 (eq. 4 with the macro model of eq. 6)
+    mu_mean = counts.astype(np.float64).mean() / oracle.n_av(w)
+    want = 1.0 / abs((1 - w.kappa_star - w.kappa_c) ** 2 - w.gamma ** 2)
+    print(f"paper-scale mean magnification {mu_mean:.3f} (theory {want:.3f})")
+    assert abs(mu_mean / want - 1) < 0.03
 
 
 # ---------------------------------------------------------------- jittered (Monte Carlo) rays

@@ -452,15 +452,22 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                 const bf16x8 b = lds8(phs + (lane & 15) * 32 + 8 * (lane >> 4));
                 g1[T4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1[T4], 0, 0, 0);
             }
-            // bias gradients and dW3: lane = hidden unit
+            // bias gradients and dW3: lane = hidden unit (16-byte loads, sums in sample order)
             {
                 float s1 = 0.f, s2 = 0.f, w0 = 0.f, w1 = 0.f;
-                for (int s = 0; s < 32; ++s) {
-                    s2 += from_bf16(z2s[lane * 32 + s]);
-                    s1 += from_bf16(z1s[lane * 32 + s]);
-                    const float h = from_bf16(h2s[lane * 32 + s]);
-                    w0 = fmaf(d3s[s], h, w0);
-                    w1 = fmaf(d3s[32 + s], h, w1);
+#pragma unroll
+                for (int s8 = 0; s8 < 32; s8 += 8) {
+                    const u16x8 vz2 = *reinterpret_cast<const u16x8 *>(z2s + lane * 32 + s8);
+                    const u16x8 vz1 = *reinterpret_cast<const u16x8 *>(z1s + lane * 32 + s8);
+                    const u16x8 vh2 = *reinterpret_cast<const u16x8 *>(h2s + lane * 32 + s8);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        s2 += from_bf16(vz2[e]);
+                        s1 += from_bf16(vz1[e]);
+                        const float h = from_bf16(vh2[e]);
+                        w0 = fmaf(d3s[s8 + e], h, w0);
+                        w1 = fmaf(d3s[32 + s8 + e], h, w1);
+                    }
                 }
                 gb2 += s2;
                 gb1 += s1;

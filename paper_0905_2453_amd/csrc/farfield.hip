@@ -238,6 +238,17 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 // Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024).
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
 // of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
+// GRID: the samples are the product of 64 u-values and n_samples / 64 v-values, listed
+// row-major (sample j 64 + i is (u_i, v_j)); a thread then takes one column i and four rows, so
+// x - x_l and its square are shared by its four samples, each of which still sees exactly the
+// operations of the general layout (the targets are bit-identical).
+template <bool GRID>
+__device__ __forceinline__ int sample_index(int part, int k, int tid)
+{
+    return GRID ? (16 * part + 4 * (tid >> 6) + k) * 64 + (tid & 63) : part * 1024 + k * 256 + tid;
+}
+
+template <bool GRID>
 __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
 {
     constexpr int LT = 256, T = 16, S = 4;
@@ -252,7 +263,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     float px[S], py[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = part * 1024 + k * 256 + tid;
+        const int si = sample_index<GRID>(part, k, tid);
         px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]);
         py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]);
     }
@@ -276,10 +287,12 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
 #pragma unroll
             for (int j = 0; j < T; ++j) {
                 const float4 l = L[r + j];
+                // GRID: the four samples share px[0]
+                const float dxs = px[0] - l.x, dxs2 = dxs * dxs;
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
-                    const float dx = px[k] - l.x, dy = py[k] - l.y;
-                    const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                    const float dx = GRID ? dxs : px[k] - l.x, dy = py[k] - l.y;
+                    const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, GRID ? dxs2 : dx * dx));
                     s1[k] = j == 0 ? d * dx : fmaf(d, dx, s1[k]);
                     s2[k] = j == 0 ? d * dy : fmaf(d, dy, s2[k]);
                 }
@@ -297,7 +310,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     const double a01 = h[4], a02 = h[5], j11 = h[6], j12 = h[7], j22 = h[8];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = part * 1024 + k * 256 + tid;
+        const int si = sample_index<GRID>(part, k, tid);
         const double d1 = (double)px[k] - c[0], d2 = (double)py[k] - c[1];
         const double r1 = A1[k] * kRcpBiasComp - (a01 + j11 * d1 + j12 * d2);
         const double r2 = A2[k] * kRcpBiasComp - (a02 + j12 * d1 + j22 * d2);
@@ -794,7 +807,10 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_affine, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ff_samples, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
+    if (f.grid_samples)
+        hipLaunchKernelGGL(k_ff_samples<true>, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
+    else
+        hipLaunchKernelGGL(k_ff_samples<false>, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;

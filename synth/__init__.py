@@ -289,6 +289,14 @@ def fit_samples(seed: int, n: int = 4096) -> np.ndarray:
     return (uniform(seed, STREAM_SAMPLES, 0, 2 * n).reshape(n, 2) * 2.0 - 1.0).astype(np.float32)
 
 
+def fit_samples_grid(seed: int, nu: int = 64, nv: int = 64) -> np.ndarray:
+    """nu x nv tile-local sample points on a product grid of seeded uniform abscissas in
+    [-1, 1] (u_0..u_{nu-1} times v_0..v_{nv-1}), listed row-major: point j nu + i is (u_i, v_j)."""
+    u = (uniform(seed, STREAM_SAMPLES, 0, nu + nv) * 2.0 - 1.0).astype(np.float32)
+    uu, vv = np.meshgrid(u[:nu], u[nu:])
+    return np.ascontiguousarray(np.stack([uu.ravel(), vv.ravel()], 1))
+
+
 def init_params(seed: int) -> np.ndarray:
     """Glorot-uniform initial parameters of the 16 -> 64 -> 64 -> 2 network, zero biases
     (float32, 5378 values in the order W1 [64][16], b1, W2 [64][64], b2, W3 [2][64], b3)."""

@@ -289,3 +289,35 @@ def test_moving_surrogate_error_vs_plain_moving_field():
     l1_frozen = np.abs(c_frozen - c_pl).sum() / c_pl.sum()
     print(f"moving field at t={t}: closure map L1 {l1:.2e}, frozen closure {l1_frozen:.2e}")
     assert l1 <= 1e-2 and l1_frozen > 3 * l1
+
+
+def test_product_grid_samples_fit_is_bit_identical():
+    # the product-grid layout shares x-differences between a column's samples; every sample
+    # still sees the same operations, so the model must not change by a single bit
+    torch, P = _env()
+    w = _small_field()
+    dev = torch.device("cuda:0")
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                     counts, lost, window=WIN)
+    ut = torch.from_numpy(synth.fit_samples_grid(3)).to(dev)
+    pt = torch.from_numpy(synth.init_params(3)).to(dev)
+    models = []
+    for grid in (None, (64, 64)):
+        cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=30, batch=512, lr=1e-2, sample_grid=grid)
+        model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+        ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+        P.farfield_fit(job, cfg, model, ws)
+        torch.cuda.synchronize()
+        models.append(model.cpu().numpy())
+    assert np.array_equal(models[0], models[1])
+    # samples that are not the declared product grid are refused before any launch
+    bad = torch.from_numpy(synth.fit_samples(3, 4096)).to(dev)
+    cfg = P.ff_config(bad, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, sample_grid=(64, 64))
+    model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    with pytest.raises(P.RayShootError) as ei:
+        P.farfield_fit(job, cfg, model, ws)
+    assert ei.value.status == -1

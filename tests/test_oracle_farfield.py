@@ -65,3 +65,14 @@ def test_tile_targets_small_and_normalised():
     assert abs(np.sqrt(np.mean((res / st) ** 2)) - 1) < 1e-12
     # the residual after the affine base is far smaller than the far field itself
     assert st < 1e-2 * np.linalg.norm(a0)
+
+
+def test_product_grid_samples_layout():
+    g = synth.fit_samples_grid(7, 64, 64)
+    assert g.shape == (4096, 2) and g.dtype == np.float32
+    idx = np.arange(4096)
+    assert np.array_equal(g[idx, 0], g[idx % 64, 0]) and np.array_equal(g[idx, 1], g[(idx // 64) * 64, 1])
+    assert np.all(np.abs(g) <= 1.0)
+    u, v = g[:64, 0], g[::64, 1]
+    assert len(np.unique(u)) == 64 and len(np.unique(v)) == 64
+    assert abs(u.mean()) < 0.25 and abs(v.mean()) < 0.25

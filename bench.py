@@ -215,12 +215,12 @@ def bench_surrogate(args, which=None, emit=True):
     lost = torch.zeros(1, dtype=torch.int64, device=dev)
     job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                      counts, lost)
-    # 4096 fit samples per tile: a 64 x 64 product grid of seeded uniform abscissas (the fit
-    # shares x-differences down a column; the targets are those of the same points listed freely)
-    samples = torch.from_numpy(synth.fit_samples_grid(7)).to(dev)
+    # 4096 seeded uniform fit samples per tile, in quads that share their first coordinate (the
+    # fit shares x-differences within a quad; the targets are those of the same points listed freely)
+    samples = torch.from_numpy(synth.fit_samples_quads(7)).to(dev)
     init = torch.from_numpy(synth.init_params(7)).to(dev)
     cfg = P.ff_config(samples, init, tile_rays=tile, r_near=8.0, steps=args.ff_steps, batch=512, lr=1e-2,
-                      sample_grid=(64, 64))
+                      shared_x=True)
     model = torch.empty(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
     fws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
     ews = torch.empty(P.farfield_eval_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
@@ -255,7 +255,7 @@ def bench_surrogate(args, which=None, emit=True):
         sys.exit(3)
     # the judged tiles: surrogate, affine-only ablation, plain direct sum
     sub_cfg = P.ff_config(samples, init, tile_rays=tile, r_near=8.0, steps=args.ff_steps, batch=512, lr=1e-2,
-                          eval_tiles=judge_t, sample_grid=(64, 64))
+                          eval_tiles=judge_t, shared_x=True)
 
     def surrogate_map(flags):
         counts.zero_()
@@ -323,7 +323,7 @@ def bench_surrogate(args, which=None, emit=True):
         "ms_per_step": 1e3 * (fit_s + eval_s), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": w.name, "n_lens": w.n_lens, "ray_grid": list(w.grid_n), "map": list(w.map_n),
-                   "tile_rays": list(tile), "r_near": 8.0, "fit_samples": "4096 (64 x 64 seeded product grid)", "adam_steps": args.ff_steps,
+                   "tile_rays": list(tile), "r_near": 8.0, "fit_samples": "4096 seeded uniform, quads sharing x", "adam_steps": args.ff_steps,
                    "judged_tiles": int(len(judge)), "n_tiles": int(n_tiles), "parallelism": "1 GPU"},
         "fit_s": fit_s, "eval_s": eval_s, "plain_s_on_judged_tiles": plain_s,
         "rays_per_s": {"surrogate_eval": sur_rays_s, "surrogate_end_to_end": e2e_rays_s, "plain": plain_rays_s},

@@ -227,11 +227,10 @@ typedef struct {
     float *debug_targets;       /* device, nullable: n_tiles x n_samples x 2 residual samples        */
     const int32_t *eval_tiles;  /* device, nullable: rs_farfield_eval shoots only these tile indices  */
     int32_t n_eval_tiles;       /* entries of eval_tiles (each in [0, n_tiles), distinct)             */
-    int32_t sample_grid[2];     /* {0, 0}: arbitrary samples.  {64, n_samples / 64}: the samples are   */
-                                /* the product of 64 u-values and n_samples / 64 v-values, listed     */
-                                /* row-major (sample j 64 + i = (u_i, v_j)); the fit checks this on   */
-                                /* the host (synchronising the stream) and shares the x-differences   */
-                                /* of a column's samples.  The fitted model is bit-identical either way. */
+    int32_t shared_x;           /* 0: arbitrary samples.  1: samples 64 (4 g + k) + i, k = 0..3, share  */
+                                /* their first coordinate (every g < n_samples / 256, i < 64): the fit */
+                                /* checks this on the host (synchronising the stream) and shares      */
+                                /* x - x_l between them.  The fitted model is bit-identical either way. */
 } rs_ff_config;
 
 /*

@@ -255,10 +255,11 @@ FFConfig = _abi.FFConfig
 
 
 def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, batch=512, lr=1e-2,
-              cell_size=0.0, debug_grad=None, debug_targets=None, eval_tiles=None, sample_grid=None) -> FFConfig:
+              cell_size=0.0, debug_grad=None, debug_targets=None, eval_tiles=None, shared_x=False) -> FFConfig:
     """rs_ff_config from device tensors: samples (n x 2 float32 in [-1,1]^2), init_params (5378 float32).
 
-    sample_grid=(64, n / 64) declares the samples a row-major product grid (faster fit)."""
+    shared_x=True declares that samples 64 (4 g + k) + i, k = 0..3, share their first coordinate
+    (faster fit, same model)."""
     torch = _torch()
     _require_cuda(samples, "samples", torch.float32)
     _require_cuda(init_params, "init_params", torch.float32)
@@ -278,8 +279,7 @@ def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, 
     if eval_tiles is not None:
         _require_cuda(eval_tiles, "eval_tiles", torch.int32)
         c.eval_tiles, c.n_eval_tiles = eval_tiles.data_ptr(), int(eval_tiles.numel())
-    if sample_grid is not None:
-        c.sample_grid[0], c.sample_grid[1] = int(sample_grid[0]), int(sample_grid[1])
+    c.shared_x = 1 if shared_x else 0
     return c
 
 

@@ -60,7 +60,7 @@ class FFConfig(ctypes.Structure):
                 ("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("cell_size", ctypes.c_double), ("samples", ctypes.c_void_p), ("init_params", ctypes.c_void_p),
                 ("debug_grad", ctypes.c_void_p), ("debug_targets", ctypes.c_void_p),
-                ("eval_tiles", ctypes.c_void_p), ("n_eval_tiles", ctypes.c_int32), ("sample_grid", c_int32_2)]
+                ("eval_tiles", ctypes.c_void_p), ("n_eval_tiles", ctypes.c_int32), ("shared_x", ctypes.c_int32)]
 
 
 class Zoom(ctypes.Structure):

@@ -238,9 +238,8 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 // Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024).
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
 // of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
-// GRID: the samples are the product of 64 u-values and n_samples / 64 v-values, listed
-// row-major (sample j 64 + i is (u_i, v_j)); a thread then takes one column i and four rows, so
-// x - x_l and its square are shared by its four samples, each of which still sees exactly the
+// GRID: samples 64 (4 g + k) + i, k = 0..3, share their first coordinate; a thread takes those
+// four, so x - x_l and its square are shared by them, and each sample still sees exactly the
 // operations of the general layout (the targets are bit-identical).
 template <bool GRID>
 __device__ __forceinline__ int sample_index(int part, int k, int tid)

@@ -397,10 +397,7 @@ int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g, bool eval 
         return fail(RS_EINVAL, "batch must be a multiple of 128 dividing n_samples");
     if (!(c->lr >= 0.0f) || !std::isfinite(c->lr)) return fail(RS_EINVAL, "lr must be finite and >= 0");
     if (!(c->cell_size >= 0.0) || !std::isfinite(c->cell_size)) return fail(RS_EINVAL, "cell_size must be >= 0");
-    if (c->sample_grid[0] || c->sample_grid[1]) {
-        if (c->sample_grid[0] != 64 || (int64_t)c->sample_grid[0] * c->sample_grid[1] != c->n_samples)
-            return fail(RS_EINVAL, "sample_grid must be {64, n_samples / 64} or {0, 0}");
-    }
+    if (c->shared_x != 0 && c->shared_x != 1) return fail(RS_EINVAL, "shared_x must be 0 or 1");
     g.TX = c->tile_rays[0];
     g.TY = c->tile_rays[1];
     g.tiles_x = (job->grid.win_n[0] + g.TX - 1) / g.TX;
@@ -769,20 +766,19 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
     if (g.n_tiles == 0) return RS_OK;
     uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
     rs::FarArgs f = far_args(job, cfg, g);
-    if (cfg->sample_grid[0]) {
-        // the product layout is a promise about the sample values: check it
-        const int nu = cfg->sample_grid[0], nv = cfg->sample_grid[1];
+    if (cfg->shared_x) {
+        // the shared first coordinates are a promise about the sample values: check it
         std::vector<float> smp((size_t)cfg->n_samples * 2);
         hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
         hipError_t e = hipMemcpyAsync(smp.data(), cfg->samples, smp.size() * sizeof(float), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) return dev_fail(e, "sample read");
-        for (int j = 0; j < nv; ++j)
-            for (int i = 0; i < nu; ++i) {
-                const size_t q = 2 * ((size_t)j * nu + i);
-                if (smp[q] != smp[2 * (size_t)i] || smp[q + 1] != smp[2 * (size_t)j * nu + 1])
-                    return fail(RS_EINVAL, "samples are not the product grid sample_grid declares (sample %d, %d)", i, j);
-            }
+        for (int g4 = 0; g4 < cfg->n_samples / 256; ++g4)
+            for (int k = 1; k < 4; ++k)
+                for (int i = 0; i < 64; ++i)
+                    if (smp[2 * ((size_t)(4 * g4 + k) * 64 + i)] != smp[2 * ((size_t)(4 * g4) * 64 + i)])
+                        return fail(RS_EINVAL, "samples %d and %d do not share their first coordinate",
+                                    (4 * g4 + k) * 64 + i, 4 * g4 * 64 + i);
         f.grid_samples = 1;
     }
     f.model = static_cast<uint8_t *>(model);

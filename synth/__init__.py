@@ -289,12 +289,16 @@ def fit_samples(seed: int, n: int = 4096) -> np.ndarray:
     return (uniform(seed, STREAM_SAMPLES, 0, 2 * n).reshape(n, 2) * 2.0 - 1.0).astype(np.float32)
 
 
-def fit_samples_grid(seed: int, nu: int = 64, nv: int = 64) -> np.ndarray:
-    """nu x nv tile-local sample points on a product grid of seeded uniform abscissas in
-    [-1, 1] (u_0..u_{nu-1} times v_0..v_{nv-1}), listed row-major: point j nu + i is (u_i, v_j)."""
-    u = (uniform(seed, STREAM_SAMPLES, 0, nu + nv) * 2.0 - 1.0).astype(np.float32)
-    uu, vv = np.meshgrid(u[:nu], u[nu:])
-    return np.ascontiguousarray(np.stack([uu.ravel(), vv.ravel()], 1))
+def fit_samples_quads(seed: int, n: int = 4096) -> np.ndarray:
+    """n tile-local sample points in [-1, 1]^2 (n a multiple of 256), each coordinate a seeded
+    uniform draw, except that samples 64 (4 g + k) + i, k = 0..3, share their first coordinate
+    (one draw per quad): n / 4 distinct first and n distinct second coordinates."""
+    d = uniform(seed, STREAM_SAMPLES, 0, n // 4 + n) * 2.0 - 1.0
+    x = d[: n // 4].reshape(n // 256, 1, 64)
+    pts = np.empty((n // 256, 4, 64, 2))
+    pts[..., 0] = x
+    pts[..., 1] = d[n // 4:].reshape(n // 256, 4, 64)
+    return np.ascontiguousarray(pts.reshape(n, 2).astype(np.float32))
 
 
 def init_params(seed: int) -> np.ndarray:

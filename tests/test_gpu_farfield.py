@@ -291,9 +291,9 @@ def test_moving_surrogate_error_vs_plain_moving_field():
     assert l1 <= 1e-2 and l1_frozen > 3 * l1
 
 
-def test_product_grid_samples_fit_is_bit_identical():
-    # the product-grid layout shares x-differences between a column's samples; every sample
-    # still sees the same operations, so the model must not change by a single bit
+def test_shared_x_samples_fit_is_bit_identical():
+    # samples in quads sharing their first coordinate let the fit share x-differences; every
+    # sample still sees the same operations, so the model must not change by a single bit
     torch, P = _env()
     w = _small_field()
     dev = torch.device("cuda:0")
@@ -302,20 +302,20 @@ def test_product_grid_samples_fit_is_bit_identical():
     lost = torch.zeros(1, dtype=torch.int64, device=dev)
     job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                      counts, lost, window=WIN)
-    ut = torch.from_numpy(synth.fit_samples_grid(3)).to(dev)
+    ut = torch.from_numpy(synth.fit_samples_quads(3)).to(dev)
     pt = torch.from_numpy(synth.init_params(3)).to(dev)
     models = []
-    for grid in (None, (64, 64)):
-        cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=30, batch=512, lr=1e-2, sample_grid=grid)
+    for shared in (False, True):
+        cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=30, batch=512, lr=1e-2, shared_x=shared)
         model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
         ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
         P.farfield_fit(job, cfg, model, ws)
         torch.cuda.synchronize()
         models.append(model.cpu().numpy())
     assert np.array_equal(models[0], models[1])
-    # samples that are not the declared product grid are refused before any launch
+    # samples that do not share their first coordinates as declared are refused before any launch
     bad = torch.from_numpy(synth.fit_samples(3, 4096)).to(dev)
-    cfg = P.ff_config(bad, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, sample_grid=(64, 64))
+    cfg = P.ff_config(bad, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, shared_x=True)
     model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
     ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
     with pytest.raises(P.RayShootError) as ei:

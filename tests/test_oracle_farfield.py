@@ -67,12 +67,10 @@ def test_tile_targets_small_and_normalised():
     assert st < 1e-2 * np.linalg.norm(a0)
 
 
-def test_product_grid_samples_layout():
-    g = synth.fit_samples_grid(7, 64, 64)
-    assert g.shape == (4096, 2) and g.dtype == np.float32
-    idx = np.arange(4096)
-    assert np.array_equal(g[idx, 0], g[idx % 64, 0]) and np.array_equal(g[idx, 1], g[(idx // 64) * 64, 1])
-    assert np.all(np.abs(g) <= 1.0)
-    u, v = g[:64, 0], g[::64, 1]
-    assert len(np.unique(u)) == 64 and len(np.unique(v)) == 64
-    assert abs(u.mean()) < 0.25 and abs(v.mean()) < 0.25
+def test_quad_samples_layout():
+    g = synth.fit_samples_quads(7, 4096)
+    assert g.shape == (4096, 2) and g.dtype == np.float32 and np.all(np.abs(g) <= 1.0)
+    q = g.reshape(16, 4, 64, 2)
+    assert np.array_equal(q[:, 1:, :, 0], np.broadcast_to(q[:, :1, :, 0], (16, 3, 64)))
+    assert len(np.unique(g[:, 0])) == 1024 and len(np.unique(g[:, 1])) == 4096
+    assert abs(g[:, 0].mean()) < 0.1 and abs(g[:, 1].mean()) < 0.1

@@ -456,7 +456,7 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch

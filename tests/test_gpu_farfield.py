@@ -2,7 +2,7 @@
 
 Checked against the FP64 oracles (oracle/farfield.py for the affine base and the exact
 far-field samples, oracle/mlp.py with bfloat16 operand emulation for the gradient and
-training), and against the plain direct sum (rs_shoot) as the judge of the map error.
+training), and against the plain direct sum (rs_shoot) as the reference for the map error.
 Surrogate tolerance: map L1 relative error sum|N_s - N_p| / sum N_p <= 1% at the stated ray
 density; the affine base alone (network off) must fail that bound.
 """

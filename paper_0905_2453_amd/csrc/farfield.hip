@@ -29,12 +29,8 @@ using f32x4 = float __attribute__((ext_vector_type(4)));
 constexpr double kRcpBiasComp = 1.0 + 6.41e-9;  // see direct.hip: mean bias of v_rcp_f32
 constexpr float kPadCoord = 1.0e18f;
 
-__device__ __forceinline__ uint16_t to_bf16(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ bf16x8 lds8(const uint16_t *p)
@@ -117,14 +113,16 @@ __device__ __forceinline__ void features8(float u, uint16_t *out)
     }
 }
 
-// Forward pass of 32 samples (one per lane pair) through layers 1 and 2: returns z1, z2 and
-// the bfloat16 activations h1, h2 in the slot layout, and the network output (both lanes).
+// Forward pass of 32 samples (one per lane pair) through layers 1 and 2: returns the bfloat16
+// activations h1, h2 in the slot layout and the network output (both lanes); with TRAIN also
+// the SiLU derivatives silu'(z) = s (1 + z (1 - s)), s = sigmoid(z), that the backward pass needs.
 struct Fwd {
-    float z1[32], z2[32];
+    float d1[32], d2[32];
     uint16_t h1[32], h2[32];
     float o[2];
 };
 
+template <bool TRAIN>
 __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint16_t *phi8, int lane,
                                           Fwd &r)
 {
@@ -139,8 +137,9 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const float z = acc[q] + sbias[slot_unit(16 * T + q, hf)];
-            r.z1[16 * T + q] = z;
-            r.h1[16 * T + q] = to_bf16(z * sigm(z));
+            const float sg = sigm(z);
+            if (TRAIN) r.d1[16 * T + q] = sg * (1.0f + z * (1.0f - sg));
+            r.h1[16 * T + q] = to_bf16(z * sg);
         }
     }
 #pragma unroll
@@ -155,8 +154,9 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const float z = acc[q] + sbias[64 + slot_unit(16 * T + q, hf)];
-            r.z2[16 * T + q] = z;
-            r.h2[16 * T + q] = to_bf16(z * sigm(z));
+            const float sg = sigm(z);
+            if (TRAIN) r.d2[16 * T + q] = sg * (1.0f + z * (1.0f - sg));
+            r.h2[16 * T + q] = to_bf16(z * sg);
         }
     }
     float po0 = 0.f, po1 = 0.f;
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
             uint16_t phi8[8];
             features8(u, phi8);
             Fwd fw;
-            forward32(Wbf, sbias, phi8, lane, fw);
+            forward32<true>(Wbf, sbias, phi8, lane, fw);
             const float inv_b = 1.0f / (float)f.batch;
             const float d30 = (fw.o[0] - t0) * inv_b, d31 = (fw.o[1] - t1) * inv_b;
             // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3
@@ -409,8 +409,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
             for (int q = 0; q < 32; ++q) {
                 const int un = slot_unit(q, hf);
                 const float dh = fmaf(from_bf16(Wbf[kOffW3 + un]), d30, from_bf16(Wbf[kOffW3 + 64 + un]) * d31);
-                const float s = sigm(fw.z2[q]);
-                dz2[q] = to_bf16(dh * (s * (1.0f + fw.z2[q] * (1.0f - s))));
+                dz2[q] = to_bf16(dh * fw.d2[q]);
             }
             // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
             uint16_t dz1[32];
@@ -424,11 +423,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(dz2 + 8 * kk), acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const float z = fw.z1[16 * T + q];
-                    const float s = sigm(z);
-                    dz1[16 * T + q] = to_bf16(acc[q] * (s * (1.0f + z * (1.0f - s))));
-                }
+                for (int q = 0; q < 16; ++q) dz1[16 * T + q] = to_bf16(acc[q] * fw.d1[16 * T + q]);
             }
             // stage [unit][sample] copies for the weight gradients
 #pragma unroll
@@ -716,7 +711,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
             uint16_t phi8[8];
             features8(u, phi8);
             Fwd fw;
-            forward32(Wbf, sbias, phi8, lane, fw);
+            forward32<false>(Wbf, sbias, phi8, lane, fw);
             o0 = fw.o[0];
             o1 = fw.o[1];
         }

@@ -1004,18 +1004,23 @@ int rs_plan_grid(const rs_map *map, const rs_macro *macro, double kappa_star, do
     }
     const double pix = ((map->hi[0] - map->lo[0]) / map->n[0]) * ((map->hi[1] - map->lo[1]) / map->n[1]);
     const double t0 = std::sqrt(pix / n_av);
+    if (!is_fin(pix) || !(pix > 0.0) || !is_fin(t0)) return fail(RS_ERANGE, "pixel area out of range");
     const double ext = std::max(std::fabs(cen[0]) + half[0], std::fabs(cen[1]) + half[1]) + lens_extent;
     if (!is_fin(ext) || ext > kMaxCoord) return fail(RS_EINVAL, "planned region too large");
     const double q = std::ldexp(1.0, std::ilogb(std::max(ext, 1e-30)) - 22);   // 2 ulp32 of ext
     const double t = std::floor(t0 / q) * q;
     if (!(t > 0.0)) return fail(RS_ERANGE, "n_av too high: cell below the float32 lattice of the region");
+    if (!is_fin(t)) return fail(RS_ERANGE, "cell size out of range");
     for (int k = 0; k < 2; ++k) {
-        const double n = std::ceil(2.0 * half[k] / t);
+        const double n = std::max(1.0, std::ceil(2.0 * half[k] / t));
         if (n >= 2147483648.0) return fail(RS_ERANGE, "axis %d needs 2^31 rays or more", k);
         const double c = std::round(cen[k] / t) * t;
         out->n[k] = (int64_t)n;
         out->lo[k] = c - 0.5 * n * t;
         out->hi[k] = c + 0.5 * n * t;
+        if (!is_fin(out->lo[k]) || !is_fin(out->hi[k]) || std::fabs(out->lo[k]) > kMaxCoord ||
+            std::fabs(out->hi[k]) > kMaxCoord)
+            return fail(RS_ERANGE, "planned region out of range");
         out->win_lo[k] = 0;
         out->win_n[k] = (int64_t)n;
     }

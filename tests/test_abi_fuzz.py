@@ -113,3 +113,86 @@ def test_plan_grid_never_crashes_and_meets_budget(n_av, ks, kc, g, ext, margin, 
         o.flags = _abi.RS_FLAG_FAULT_INJECT
         if math.isfinite(kc) and math.isfinite(g):
             assert L.rs_shoot(ctypes.byref(j), ctypes.c_void_p(0x4000), 1 << 62, None, ctypes.byref(o)) in (EDEVICE, ERANGE)
+
+
+def _valid_job(_abi):
+    j = _abi.Job()
+    j.lenses = ctypes.c_void_p(0x1000)
+    j.n_lens = 10
+    j.macro.kappa_c, j.macro.gamma = 0.0, 0.1
+    for k in range(2):
+        j.grid.lo[k], j.grid.hi[k], j.grid.n[k] = -1.0, 1.0, 256
+        j.grid.win_lo[k], j.grid.win_n[k] = 0, 256
+        j.map.lo[k], j.map.hi[k], j.map.n[k] = -1.0, 1.0, 32
+    j.counts, j.n_lost = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    return j
+
+
+@settings(max_examples=300, deadline=None)
+@given(tx=st.integers(-2, 300), ty=st.integers(-2, 300), r_near=floats, ns=st.integers(-1, 9000),
+       steps=st.integers(-2, 5000), batch=st.integers(-1, 5000), lr=floats, cell=floats,
+       shared=st.integers(-1, 2))
+def test_farfield_config_validation_never_crashes(tx, ty, r_near, ns, steps, batch, lr, cell, shared):
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    j = _valid_job(_abi)
+    c = _abi.FFConfig()
+    c.tile_rays[0], c.tile_rays[1] = tx, ty
+    c.r_near, c.n_samples, c.steps, c.batch = r_near, ns, steps, batch
+    c.lr = lr if abs(lr) < 3e38 or not math.isfinite(lr) else 1.0
+    c.cell_size, c.shared_x = cell, shared
+    c.samples, c.init_params = 0x5000, 0x6000
+    nb = L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c))
+    valid = (tx > 0 and ty > 0 and math.isfinite(r_near) and r_near > 0 and ns > 0 and ns % 1024 == 0
+             and steps >= 0 and batch > 0 and batch % 128 == 0 and ns % batch == 0 and math.isfinite(c.lr)
+             and c.lr >= 0 and math.isfinite(cell) and cell >= 0 and shared in (0, 1))
+    assert (nb > 0) == valid
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    ws = L.rs_farfield_eval_workspace_bytes(ctypes.byref(j), ctypes.byref(c))
+    r = L.rs_farfield_eval(ctypes.byref(j), ctypes.byref(c), ctypes.c_void_p(0x7000), max(nb, 1) << 1,
+                           ctypes.c_void_p(0x8000), max(ws, 1) << 1, None, ctypes.byref(o))
+    assert r in ((EDEVICE,) if valid else (EINVAL, ERANGE))
+
+
+@settings(max_examples=300, deadline=None)
+@given(c1=st.integers(-2, 70000), c2=st.integers(-2, 70000), margin=floats)
+def test_zoom_parameters_never_crash(c1, c2, margin):
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    j = _valid_job(_abi)
+    z = _abi.Zoom()
+    z.cell[0], z.cell[1], z.margin = c1, c2, margin
+    need = L.rs_zoom_workspace_bytes(ctypes.byref(j), ctypes.byref(z), None)
+    valid = (0 <= c1 <= 65536 and 0 <= c2 <= 65536 and (c1 == 0) == (c2 == 0) and math.isfinite(margin)
+             and margin >= 0)
+    assert (need > 0) == valid
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    r = L.rs_shoot_zoom(ctypes.byref(j), ctypes.byref(z), ctypes.c_void_p(0x4000), max(need, 1), None, ctypes.byref(o))
+    assert r == (EDEVICE if valid else EINVAL)
+
+
+@settings(max_examples=200, deadline=None)
+@given(bad=st.lists(st.integers(0, 5), min_size=1, max_size=6))
+def test_batched_validation_never_crashes(bad):
+    # 0: valid job; 1: negative lenses; 2: inverted grid; 3: NULL counts; 4: window outside; 5: map too big
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+    jobs = []
+    for b in bad:
+        j = _valid_job(_abi)
+        if b == 1:
+            j.n_lens = -1
+        elif b == 2:
+            j.grid.hi[0] = -2.0
+        elif b == 3:
+            j.counts = ctypes.c_void_p(0)
+        elif b == 4:
+            j.grid.win_lo[1] = 200
+        elif b == 5:
+            j.map.n[0], j.map.n[1] = 65536, 65536
+        jobs.append(j)
+    arr = (_abi.Job * len(jobs))(*jobs)
+    need = L.rs_batched_workspace_bytes(arr, len(jobs))
+    assert (need > 0) == all(b == 0 for b in bad)

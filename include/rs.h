@@ -350,13 +350,17 @@ typedef struct {
  * counts: device map, map->n[1] rows of map->n[0] uint32 (the layout rs_shoot fills).
  * tracks: device, n_tracks x 4 doubles (start1, start2, end1, end2), finite.
  * mu, mag: device outputs of n_tracks x n_points doubles, track-major (either may be NULL).
+ * frame_stride: 0 reads one map for every point; otherwise point k of every track reads the
+ * map at counts + k frame_stride (a time-evolving field, section 5: one frame per point, e.g.
+ * the maps of a batch of moving-lens jobs); frame_stride >= map->n[0] map->n[1].
  * Nothing is allocated; asynchronous on `stream`.  n_tracks = 0 is a no-op.
- * Errors: RS_EINVAL for a bad map, n_av <= 0, source or sizes; RS_EDEVICE if the launch fails.
- * A non-finite track coordinate is not detected (the tracks live on the device) and gives NaN.
+ * Errors: RS_EINVAL for a bad map, n_av <= 0, source, sizes or stride; RS_EDEVICE if the launch
+ * fails.  A non-finite track coordinate is not detected (the tracks live on the device) and
+ * gives NaN.
  */
 int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,
-                   const double *tracks, int32_t n_tracks, int32_t n_points, double *mu, double *mag,
-                   void *stream);
+                   const double *tracks, int32_t n_tracks, int32_t n_points, int64_t frame_stride, double *mu,
+                   double *mag, void *stream);
 
 /* Destroy the cached batch graphs and staged job tables (e.g. before freeing workspaces). */
 void rs_release_graphs(void);

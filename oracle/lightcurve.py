@@ -36,8 +36,18 @@ def _support(kind: str, size: float, cutoff: float) -> float:
 def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gaussian", size=0.1,
                 cutoff=0.0, sums=False):
     """mu and delta-m, each (n_tracks, n_points); with sums=True also the weighted count sum and
-    the weight sum of every point."""
-    counts = np.asarray(counts).reshape(int(map_n[1]), int(map_n[0])).astype(np.float64)
+    the weight sum of every point.
+
+    counts is one map read by every point, or a stack of n_points maps of which point k reads
+    map k (a field whose lenses move between the frames, section 5)."""
+    pix = int(map_n[0]) * int(map_n[1])
+    counts = np.asarray(counts)
+    if counts.size == pix:
+        frames = [counts.reshape(int(map_n[1]), int(map_n[0])).astype(np.float64)] * n_points
+    elif counts.size == pix * n_points:
+        frames = [f.astype(np.float64) for f in counts.reshape(n_points, int(map_n[1]), int(map_n[0]))]
+    else:
+        raise ValueError("counts must hold one map or n_points maps")
     tracks = np.asarray(tracks, dtype=np.float64).reshape(-1, 4)
     w0 = (map_hi[0] - map_lo[0]) / map_n[0]
     w1 = (map_hi[1] - map_lo[1]) / map_n[1]
@@ -60,7 +70,7 @@ def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gau
             inside = r2 <= R * R
             wgt = np.exp(-r2 / (2.0 * size * size)) if kind == "gaussian" else np.ones_like(r2)
             wgt = np.where(inside, wgt, 0.0)
-            num[t, k] = np.sum(wgt * counts)
+            num[t, k] = np.sum(wgt * frames[k])
             den[t, k] = np.sum(wgt)
             mu[t, k] = num[t, k] / (den[t, k] * n_av) if den[t, k] > 0 else np.nan
     with np.errstate(divide="ignore", invalid="ignore"):

@@ -327,13 +327,22 @@ def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gau
                 cutoff=0.0, stream=None, layout=0):
     """rs_light_curve: light curves of a source profile along straight tracks over a device map.
 
+    counts: one map (map_n[1] x map_n[0]) read by every point, or a stack of n_points maps
+    (n_points x map_n[1] x map_n[0]) of which point k reads map k (a time-evolving field).
     tracks: device float64 tensor (n_tracks, 4) of (start1, start2, end1, end2).
     Returns (mu, dmag), device float64 tensors of shape (n_tracks, n_points)."""
     torch = _torch()
     _require_cuda(counts, "counts")
     _require_cuda(tracks, "tracks")
-    if counts.numel() != int(map_n[0]) * int(map_n[1]) or counts.element_size() != 4 or not counts.is_contiguous():
-        raise ValueError("counts must be the contiguous map_n[1] x map_n[0] 32-bit map")
+    pix = int(map_n[0]) * int(map_n[1])
+    if counts.element_size() != 4 or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous 32-bit map or stack of maps")
+    if counts.numel() == pix:
+        stride = 0
+    elif counts.numel() == pix * int(n_points):
+        stride = pix
+    else:
+        raise ValueError("counts must hold one map or n_points maps of map_n[1] x map_n[0] pixels")
     if tracks.dtype != torch.float64 or tracks.dim() != 2 or tracks.shape[1] != 4 or not tracks.is_contiguous():
         raise ValueError("tracks must be a contiguous (n_tracks, 4) float64 tensor")
     m = _abi.Map()
@@ -347,7 +356,7 @@ def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gau
     mu = torch.empty((nt, int(n_points)), dtype=torch.float64, device=counts.device)
     mag = torch.empty_like(mu)
     _check(lib().rs_light_curve(ctypes.c_void_p(counts.data_ptr()), ctypes.byref(m), float(n_av), ctypes.byref(s),
-                                ctypes.c_void_p(tracks.data_ptr()), nt, int(n_points),
+                                ctypes.c_void_p(tracks.data_ptr()), nt, int(n_points), stride,
                                 ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(mag.data_ptr()),
                                 _stream_handle(stream)))
     return mu, mag

@@ -103,8 +103,8 @@ EXPORTS = [
                                      ctypes.c_void_p, ctypes.POINTER(Opts)]),
     ("rs_zoom_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64 * 4), ctypes.c_void_p]),
     ("rs_light_curve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Map), ctypes.c_double, ctypes.POINTER(Source),
-                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                      ctypes.c_void_p, ctypes.c_void_p]),
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("rs_release_graphs", None, []),
 ]
 

@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(64 * kLcWaves) k_light_curve(const LightArgs a
             // e = dr * nx + dc, advanced by 64 without a division per pixel
             int dr = lane / nx, dc = lane - (lane / nx) * nx;
             const int sr = 64 / nx, sc = 64 - (64 / nx) * nx;
-            const uint32_t *base = a.counts + (int64_t)p2lo * a.n[0] + p1lo;
+            const uint32_t *base = a.counts + (int64_t)k * a.frame_stride + (int64_t)p2lo * a.n[0] + p1lo;
             for (int e = lane; e < total; e += 64) {
                 const double2 cx = s_col[wv][dc], ry = s_row[wv][dr];
                 if (cx.x + ry.x <= rs2) {
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(64 * kLcWaves) k_light_curve(const LightArgs a
                 const double d2s = d1 * d1 + d2 * d2;
                 if (d2s <= rs2) {
                     const double wgt = gauss ? exp(-d2s * inv2s2) : 1.0;
-                    num += wgt * (double)a.counts[(int64_t)p2 * a.n[0] + p1];
+                    num += wgt * (double)a.counts[(int64_t)k * a.frame_stride + (int64_t)p2 * a.n[0] + p1];
                     den += wgt;
                 }
             }
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_light_curve_lanes(const LightArgs a)
         for (int p2 = p2lo; p2 <= p2hi; ++p2) {
             const double dy = (a.lo[1] + ((double)p2 + 0.5) * w2) - ys2;
             const double dy2 = dy * dy;
-            const uint32_t *row = a.counts + (int64_t)p2 * a.n[0];
+            const uint32_t *row = a.counts + (int64_t)k * a.frame_stride + (int64_t)p2 * a.n[0];
             double gx = gx0, rx = rx0;
             for (int p1 = p1lo; p1 <= p1hi; ++p1) {
                 const double dx = (a.lo[0] + ((double)p1 + 0.5) * w1) - ys1;

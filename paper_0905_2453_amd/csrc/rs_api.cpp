@@ -1047,8 +1047,8 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
 
 
 int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const rs_source *src,
-                   const double *tracks, int32_t n_tracks, int32_t n_points, double *mu, double *mag,
-                   void *stream)
+                   const double *tracks, int32_t n_tracks, int32_t n_points, int64_t frame_stride, double *mu,
+                   double *mag, void *stream)
 {
     g_err[0] = '\0';
     if (!map || !src) return fail(RS_EINVAL, "map and source are required");
@@ -1064,6 +1064,9 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     if (!(src->size > 0.0) || !std::isfinite(src->size)) return fail(RS_EINVAL, "source size must be finite and > 0");
     if (!(src->cutoff >= 0.0) || !std::isfinite(src->cutoff)) return fail(RS_EINVAL, "cutoff must be finite and >= 0");
     if (src->layout < 0 || src->layout > 2) return fail(RS_EINVAL, "layout must be 0, 1 or 2");
+    if (frame_stride != 0 && frame_stride < (int64_t)map->n[0] * map->n[1])
+        return fail(RS_EINVAL, "frame_stride must be 0 or at least one map (%lld words)",
+                    (long long)map->n[0] * map->n[1]);
     if (n_tracks == 0) return RS_OK;
     if (!counts || !tracks) return fail(RS_EINVAL, "counts and tracks are required");
     rs::LightArgs a{};
@@ -1085,6 +1088,7 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     a.mu = mu;
     a.mag = mag;
     a.path = src->layout;
+    a.frame_stride = frame_stride;
     const hipError_t e = rs::launch_light_curve(a, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RS_OK : dev_fail(e, "light-curve launch");
 }

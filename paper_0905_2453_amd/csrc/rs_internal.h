@@ -196,6 +196,7 @@ struct LightArgs {
     int32_t n_tracks, n_points;
     double *mu, *mag;       // n_tracks x n_points each (either may be null)
     int32_t path;           // 0: chosen by size, 1: lane per point, 2: wave per point
+    int64_t frame_stride;   // words between the maps of consecutive track points (0: one map)
 };
 
 hipError_t launch_light_curve(const LightArgs &a, hipStream_t s);

@@ -263,17 +263,17 @@ def test_light_curve_validation_without_device():
         s.kind, s.size, s.cutoff = kind, size, cutoff
         return s
 
-    def call(mp=m, n_av=4.0, s=None, nt=3, npts=10, counts=0x1000, tracks=0x2000):
+    def call(mp=m, n_av=4.0, s=None, nt=3, npts=10, counts=0x1000, tracks=0x2000, stride=0):
         s = s if s is not None else src()
         return L.rs_light_curve(ctypes.c_void_p(counts), ctypes.byref(mp), n_av, ctypes.byref(s),
-                                ctypes.c_void_p(tracks), nt, npts, ctypes.c_void_p(0x3000), None, None)
+                                ctypes.c_void_p(tracks), nt, npts, stride, ctypes.c_void_p(0x3000), None, None)
 
     bad_map = _abi.Map()
     for k in range(2):
         bad_map.lo[k], bad_map.hi[k], bad_map.n[k] = 1.0, 1.0, 64
     for st in [call(n_av=0.0), call(n_av=float("nan")), call(s=src(kind=2)), call(s=src(size=0.0)),
                call(s=src(size=float("inf"))), call(s=src(cutoff=-1.0)), call(nt=-1), call(npts=0),
-               call(mp=bad_map), call(counts=0), call(tracks=0)]:
+               call(mp=bad_map), call(counts=0), call(tracks=0), call(stride=64 * 64 - 1), call(stride=-5)]:
         assert st == -1
     assert call(npts=0) == -1 and b"n_points" in L.rs_last_error()
     assert call(nt=0, counts=0, tracks=0) == 0          # nothing to do: no launch, no device

@@ -81,7 +81,7 @@ def test_light_curve_validation_never_crashes(n_av, size, cutoff, kind, layout, 
     if valid and nt > 0:
         return                                   # would launch: not a host-only case
     r = L.rs_light_curve(ctypes.c_void_p(0x1000), ctypes.byref(m), n_av, ctypes.byref(s), ctypes.c_void_p(0x2000),
-                         nt, npts, None, None, None)
+                         nt, npts, 0, None, None, None)
     assert r == (OK if valid else EINVAL)
 
 

@@ -142,3 +142,18 @@ def test_synth_generators():
     assert t.shape == (50, 4)
     assert np.allclose(np.hypot(t[:, 2] - t[:, 0], t[:, 3] - t[:, 1]), 1.5)
     assert (t[:, 0] >= -1).all() and (t[:, 0] < 3).all() and (t[:, 1] >= -2).all() and (t[:, 1] < 4).all()
+
+
+def test_frame_stack_reads_one_frame_per_point():
+    # uniform frames of value c_k: point k sees c_k / N_av whatever the source; identical frames
+    # reproduce the single-map curve
+    n = (24, 16)
+    vals = np.array([3, 9, 27, 81, 5], np.uint32)
+    stack = np.stack([np.full((n[1], n[0]), v, np.uint32) for v in vals])
+    tr = np.array([[2.0, 3.0, 20.0, 12.0], [5.5, 5.5, 5.5, 5.5]])
+    mu, _ = lc.light_curve(stack, (0, 0), n, n, 3.0, tr, 5, "gaussian", 1.3)
+    assert np.allclose(mu, np.broadcast_to(vals / 3.0, (2, 5)), rtol=1e-15, atol=0)
+    one = synth.count_map(8, n, 12.0)
+    mu1, _ = lc.light_curve(one, (0, 0), n, n, 3.0, tr, 5, "disc", 2.2)
+    mus, _ = lc.light_curve(np.stack([one] * 5), (0, 0), n, n, 3.0, tr, 5, "disc", 2.2)
+    assert np.array_equal(mu1, mus)

@@ -54,7 +54,9 @@ __device__ __forceinline__ int perm_row(int R)
 // logical hidden unit held in slot q (0..31) by a lane of half hf
 __device__ __forceinline__ int slot_unit(int q, int hf) { return 16 * (q >> 3) + 8 * hf + (q & 7); }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// sigmoid with the hardware reciprocal (1 ulp): its error is far below the bfloat16 rounding
+// every activation and delta goes through
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // Lens (FP32 record) within r_near of the tile rectangle, decided in FP64.
 __device__ __forceinline__ bool is_near(float lx, float ly, const double lo[2], const double hi[2], double rn2)
@@ -519,13 +521,15 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         b1t *= 0.9;
         b2t *= 0.999;
         const float lr_t = (float)((double)f.lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (step - 1) / f.steps)));
-        const float bc1 = (float)(1.0 - b1t), bc2 = (float)(1.0 - b2t);
+        // bias corrections as per-step reciprocals; the per-parameter quotient by the hardware
+        // reciprocal (1 ulp, far below the bfloat16 rounding of the weights)
+        const float ibc1 = (float)(1.0 / (1.0 - b1t)), ibc2 = (float)(1.0 / (1.0 - b2t));
         for (int p = tid; p < kNParams; p += 256) {
             const float g = red[p];
             float w = state[p], m = state[kNParams + p], v = state[2 * kNParams + p];
             m = 0.9f * m + 0.1f * g;
             v = 0.999f * v + 0.001f * g * g;
-            w -= lr_t * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+            w -= lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
             state[p] = w;
             state[kNParams + p] = m;
             state[2 * kNParams + p] = v;

@@ -302,14 +302,16 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
  * are shot: the window is split into culling cells of zoom->cell fine rays; each cell's image
  * under eq. 6 is bounded from its centre (deflection, its gradient, a second-order remainder
  * over the lenses beyond three half-diagonals, 2 m / distance for closer lenses; a cell that
- * holds a lens is always kept), widened by a float32 rounding allowance and zoom->margin; the
- * rays of the cells whose bound meets the map are shot with the plain path's arithmetic.
+ * holds a lens is always kept), widened by a float32 rounding allowance and zoom->margin.  The
+ * bounds are taken coarse to fine over three levels (cells grouped 4 x 4, then 16 x 16), a
+ * level looking only inside the cells kept above it; the rays of the finest cells kept are
+ * shot with the plain path's arithmetic.
  * *job->n_lost receives only the shot rays that miss the map.  opts as for rs_shoot, except
  * that per-ray dumps are rejected (RS_EINVAL).
  */
 typedef struct {
-    int32_t cell[2];   /* fine rays per culling cell along each axis; {0, 0} = about 256 rays,   */
-                       /* square in the image plane, rounded up to whole lane blocks          */
+    int32_t cell[2];   /* fine rays per (finest) culling cell along each axis; {0, 0} = about   */
+                       /* 64 rays, square in the image plane, rounded up to whole lane blocks */
     double margin;     /* extra source-plane distance added to every cell's bound, >= 0      */
 } rs_zoom;
 

@@ -567,8 +567,11 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
 
 struct ZoomLayout {
     int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, sx = 0, S = 0;
-    int64_t P = 4, npx = 0, npy = 0;     // culling cells per parent side, parents per axis
-    size_t parent_off = 0, list_off = 0, part_off = 0, total = 0;
+    int levels = rs::kZoomLevels;
+    int64_t P = 4;                            // cells per parent side between levels
+    int64_t lcw1[rs::kZoomLevels] = {}, lcw2[rs::kZoomLevels] = {}, lnx[rs::kZoomLevels] = {}, lny[rs::kZoomLevels] = {};
+    size_t list_off[rs::kZoomLevels] = {};
+    size_t part_off = 0, total = 0;
 };
 
 int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &L)
@@ -581,9 +584,9 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     const double t1 = (g.hi[0] - g.lo[0]) / (double)g.n[0], t2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
     int64_t c1 = z->cell[0], c2 = z->cell[1];
     if (c1 == 0 && c2 == 0) {
-        // about 256 fine rays per cell, square in the image plane, whole lane blocks
-        c1 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(std::sqrt(256.0 * t2 / t1))));
-        c2 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(256.0 / (double)c1)));
+        // about 64 fine rays per cell, square in the image plane, whole lane blocks
+        c1 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(std::sqrt(64.0 * t2 / t1))));
+        c2 = std::max<int64_t>(1, std::min<int64_t>(4096, std::llround(64.0 / (double)c1)));
         c1 = (c1 + t.K1 - 1) / t.K1 * t.K1;
         c2 = (c2 + t.K2 - 1) / t.K2 * t.K2;
     } else if (c1 == 0 || c2 == 0) {
@@ -599,13 +602,19 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     L.S = L.sx * ((c2 + t.K2 - 1) / t.K2);
     if ((uint64_t)L.cells * (uint64_t)L.S * (uint64_t)(t.K1 * t.K2) >= (uint64_t(1) << 40))
         return fail(RS_ERANGE, "too many ray slots");
-    L.npx = (L.ncx + L.P - 1) / L.P;
-    L.npy = (L.ncy + L.P - 1) / L.P;
+    // level levels-1 is the cell grid; each coarser level groups P x P cells of the next
     size_t off = 256;
-    L.parent_off = off;
-    off += align256((size_t)(L.npx * L.npy) * sizeof(uint32_t));
-    L.list_off = off;
-    off += align256((size_t)L.cells * sizeof(uint32_t));
+    for (int l = L.levels - 1; l >= 0; --l) {
+        const int64_t f = (l == L.levels - 1) ? 1 : L.P * (L.lcw1[l + 1] / L.c1);
+        L.lcw1[l] = c1 * f;
+        L.lcw2[l] = c2 * f;
+        L.lnx[l] = (g.win_n[0] + L.lcw1[l] - 1) / L.lcw1[l];
+        L.lny[l] = (g.win_n[1] + L.lcw2[l] - 1) / L.lcw2[l];
+    }
+    for (int l = 0; l < L.levels; ++l) {
+        L.list_off[l] = off;
+        off += align256((size_t)(L.lnx[l] * L.lny[l]) * sizeof(uint32_t));
+    }
     L.part_off = off;
     off += (size_t)(rs::kPartials * partial_stride(job)) * sizeof(uint32_t);
     L.total = off + 256;
@@ -918,6 +927,15 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     z.c2 = L.c2;
     z.ncx = L.ncx;
     z.ncy = L.ncy;
+    z.levels = L.levels;
+    z.P = L.P;
+    for (int l = 0; l < L.levels; ++l) {
+        z.lcw1[l] = L.lcw1[l];
+        z.lcw2[l] = L.lcw2[l];
+        z.lnx[l] = L.lnx[l];
+        z.lny[l] = L.lny[l];
+        z.lists[l] = reinterpret_cast<uint32_t *>(base + L.list_off[l]);
+    }
     z.lam1 = a.lam1;
     z.lam2 = a.lam2;
     z.zlo1 = job->map.lo[0];
@@ -933,13 +951,7 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     z.xmax = xmax;
     z.vel = a.vel;
     z.time = a.time;
-    z.P = L.P;
-    z.npx = L.npx;
-    z.npy = L.npy;
-    z.parents_out = reinterpret_cast<uint32_t *>(base + L.parent_off);
-    z.parents = z.parents_out;
-    z.n_parents = stats + 4;
-    z.list = reinterpret_cast<uint32_t *>(base + L.list_off);
+    z.list = z.lists[L.levels - 1];
     z.stats = stats;
 
     rs::CellBlocks cb{};

@@ -148,23 +148,26 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
 
 // ---------------------------------------------------------------- zoom
 
+constexpr int kZoomLevels = 3;
+
 struct ZoomArgs {
     const float4 *lenses;
     int64_t n_lens;
     double glo1, glo2, gt1, gt2;        // fine grid origin and spacing
     int64_t wlo1, wlo2, wn1, wn2;       // fine ray window
     int64_t c1, c2, ncx, ncy;           // fine rays per culling cell, cells per axis
-    int64_t P, npx, npy;                // culling cells per parent side; parents per axis
+    int32_t levels;                     // culling levels (coarsest first); the last is the cells
+    int64_t P;                          // cells per parent side between consecutive levels
+    int64_t lcw1[kZoomLevels], lcw2[kZoomLevels];   // fine rays per cell side, per level
+    int64_t lnx[kZoomLevels], lny[kZoomLevels];     // cells per axis, per level
     double lam1, lam2;
     double zlo1, zlo2, zhi1, zhi2;      // zoom map rectangle
     double margin, pad, xmax;           // caller margin; float32 coordinate allowance; max |x|
     const float2 *vel;                  // lens velocities or null
     double time;
-    uint32_t *parents_out;              // kept parent indices (level 0 output)
-    const uint32_t *parents;            // the same list, read by level 1
-    const uint32_t *n_parents;          // its length (stats + 4)
-    uint32_t *list;                     // kept cell indices
-    uint32_t *stats;                    // [0] cells kept (list length), [4] parents kept
+    uint32_t *lists[kZoomLevels];       // kept cells of each level; the last is `list`
+    uint32_t *list;                     // kept cell indices (finest level)
+    uint32_t *stats;                    // [0] cells kept (list length), [4 + l] kept at level l < levels - 1
 };
 
 hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s);

@@ -29,35 +29,34 @@ __device__ __forceinline__ float4 zoom_pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
-// One thread per cell of one culling level; kept cells are appended to `out`.
-//   level 0: the parent cells, P x P culling cells each, all of them;
-//   level 1: the culling cells inside the kept parents: thread t takes child t % P^2 of
-//            parent parents[t / P^2].
+// One thread per cell of one culling level; kept cells are appended to that level's list.
+//   level 0: every cell of the coarsest level;
+//   level l > 0: the cells inside the cells kept at level l - 1: thread t takes child t % P^2 of
+//                kept cell lists[l - 1][t / P^2].
+// A child's rectangle lies inside its parent's, so a cell whose image can meet the map is kept
+// at every level above it.
 __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int level)
 {
     __shared__ float4 s_lens[2][kZoomLT];
     const int64_t t_id = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t P = z.P, PP = z.P * z.P;
-    int64_t n_items, cx = 0, cy = 0, cw1, cw2, idx = 0;
+    const int64_t cw1 = z.lcw1[level], cw2 = z.lcw2[level];
+    int64_t n_items, cx = 0, cy = 0, idx = 0;
     if (level == 0) {
-        n_items = z.npx * z.npy;
+        n_items = z.lnx[0] * z.lny[0];
         if (t_id < n_items) {
-            cx = t_id % z.npx;
-            cy = t_id / z.npx;
+            cx = t_id % z.lnx[0];
+            cy = t_id / z.lnx[0];
             idx = t_id;
         }
-        cw1 = P * z.c1;
-        cw2 = P * z.c2;
     } else {
-        n_items = (int64_t)(*z.n_parents) * PP;
+        n_items = (int64_t)z.stats[4 + level - 1] * PP;
         if (t_id < n_items) {
-            const int64_t par = z.parents[t_id / PP], k = t_id % PP;
-            cx = (par % z.npx) * P + k % P;
-            cy = (par / z.npx) * P + k / P;
-            idx = cy * z.ncx + cx;
+            const int64_t par = z.lists[level - 1][t_id / PP], k = t_id % PP;
+            cx = (par % z.lnx[level - 1]) * P + k % P;
+            cy = (par / z.lnx[level - 1]) * P + k / P;
+            idx = cy * z.lnx[level] + cx;
         }
-        cw1 = z.c1;
-        cw2 = z.c2;
     }
     if ((int64_t)blockIdx.x * kThreads >= n_items) return;      // whole workgroup idle
     const bool active = t_id < n_items && cx * cw1 < z.wn1 && cy * cw2 < z.wn2;
@@ -148,9 +147,8 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
     if (!keep)
         keep = (y1 + E1 >= z.zlo1) && (y1 - E1 <= z.zhi1) && (y2 + E2 >= z.zlo2) && (y2 - E2 <= z.zhi2);
     if (keep) {
-        uint32_t *out = level == 0 ? z.parents_out : z.list;
-        uint32_t *cnt = level == 0 ? &z.stats[4] : &z.stats[0];
-        out[atomicAdd(cnt, 1u)] = (uint32_t)idx;
+        uint32_t *cnt = level == z.levels - 1 ? &z.stats[0] : &z.stats[4 + level];
+        z.lists[level][atomicAdd(cnt, 1u)] = (uint32_t)idx;
     }
 }
 
@@ -158,16 +156,18 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
 
 hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s)
 {
-    const int64_t parents = z.npx * z.npy;
-    if (parents <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((parents + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // level 1 over at most every child of every parent; workgroups past the kept children exit
-    const int64_t children = parents * z.P * z.P;
-    hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((children + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z,
-                       1);
-    return hipGetLastError();
+    int64_t items = z.lnx[0] * z.lny[0];
+    if (items <= 0) return hipSuccess;
+    for (int l = 0; l < z.levels; ++l) {
+        // level l > 0 runs over at most every child of every cell of level l - 1; workgroups
+        // past the kept children exit at once
+        if (l > 0) items = z.lnx[l - 1] * z.lny[l - 1] * z.P * z.P;
+        hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((items + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z,
+                           l);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rs

@@ -84,7 +84,7 @@ def test_zoom_equals_fine_grid_paper_field(block, jitter):
     cp, cz, st = _run(w, w.grid_n, (-1.25, -1.25), (1.25, 1.25), (256, 256), opts=o, jitter_seed=jitter)
     print("paper field zoom:", block, jitter, st, "counts", int(cp.sum()))
     assert cp.sum() > 0 and np.array_equal(cp, cz)
-    assert st["cells_kept"] < 0.15 * st["cells"] and st["slots_shot"] < 0.15 * st["slots"]
+    assert st["cells_kept"] < 0.06 * st["cells"] and st["slots_shot"] < 0.06 * st["slots"]
 
 
 def test_zoom_window_cells_and_margin():

@@ -408,7 +408,7 @@ def bench_zoom(P, torch, w, lenses, stream):
     exact = bool(torch.equal(cp, cz))
     rays = fine[0] * fine[1]
     return {"config": {"field": w.name, "fine_ray_grid": list(fine), "window": [list(ZOOM_LO), list(ZOOM_HI)],
-                       "map": list(ZOOM_N), "cell": "auto (~64 rays, square), 3 culling levels"},
+                       "map": list(ZOOM_N), "cell": "auto (~64 rays, square), 5 culling levels halving the cell side"},
             "zoom_s": t_zoom, "full_fine_s": t_full, "speedup_vs_full": t_full / t_zoom,
             "ray_slots_shot_frac": st["slots_shot"] / max(1, st["slots"]),
             "cells_kept_frac": st["cells_kept"] / max(1, st["cells"]),

@@ -568,7 +568,7 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
 struct ZoomLayout {
     int64_t c1 = 0, c2 = 0, ncx = 0, ncy = 0, cells = 0, sx = 0, S = 0;
     int levels = rs::kZoomLevels;
-    int64_t P = 4;                            // cells per parent side between levels
+    int64_t P = 2;                            // cells per parent side between levels
     int64_t lcw1[rs::kZoomLevels] = {}, lcw2[rs::kZoomLevels] = {}, lnx[rs::kZoomLevels] = {}, lny[rs::kZoomLevels] = {};
     size_t list_off[rs::kZoomLevels] = {};
     size_t part_off = 0, total = 0;
@@ -898,7 +898,8 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     uint32_t *stats = reinterpret_cast<uint32_t *>(base);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // statistics: [0] kept cells (the list length), [1] cells, [2] lane blocks per cell,
-    // [3] rays per lane block, [4] kept parents
+    // [3] rays per lane block, [4 + l] kept cells of the coarser level l < levels - 1
+    static_assert(rs::kZoomLevels <= 5, "the statistics block holds four coarser levels");
     hipError_t e = rs::launch_fill_u32(stats, 8, 0u, s);
     if (e == hipSuccess) e = rs::launch_fill_u32(stats + 1, 1, (uint32_t)L.cells, s);
     if (e == hipSuccess) e = rs::launch_fill_u32(stats + 2, 1, (uint32_t)L.S, s);

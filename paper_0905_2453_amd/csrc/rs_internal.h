@@ -148,7 +148,7 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
 
 // ---------------------------------------------------------------- zoom
 
-constexpr int kZoomLevels = 3;
+constexpr int kZoomLevels = 5;   // culling levels, each halving the cell side of the one above
 
 struct ZoomArgs {
     const float4 *lenses;

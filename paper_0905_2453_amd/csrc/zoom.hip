@@ -15,6 +15,8 @@
 // unbounded.  A cell whose bounding box, widened by a rounding allowance, misses the window cannot
 // contribute and is skipped; the rays of the kept cells are shot exactly as the plain path shoots
 // them, so the zoom map equals the full fine-grid map on the window.
+#include <algorithm>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -29,16 +31,21 @@ __device__ __forceinline__ float4 zoom_pad_lens()
     return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
 }
 
-// One thread per cell of one culling level; kept cells are appended to that level's list.
+// One work item per cell of one culling level; kept cells are appended to that level's list.
 //   level 0: every cell of the coarsest level;
-//   level l > 0: the cells inside the cells kept at level l - 1: thread t takes child t % P^2 of
+//   level l > 0: the cells inside the cells kept at level l - 1: item t takes child t % P^2 of
 //                kept cell lists[l - 1][t / P^2].
 // A child's rectangle lies inside its parent's, so a cell whose image can meet the map is kept
 // at every level above it.
-__global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int level)
+//
+// ks (1, 2, 4, 8 or 16) consecutive lanes share a cell, each summing every ks-th run of the lens
+// tile, so coarse levels with few cells still fill the GPU; the partial sums then meet in a fixed
+// butterfly and the first lane of the group decides.
+__global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int level, int ks)
 {
     __shared__ float4 s_lens[2][kZoomLT];
-    const int64_t t_id = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int part = threadIdx.x & (ks - 1);
+    const int64_t t_id = (int64_t)blockIdx.x * (kThreads / ks) + threadIdx.x / ks;
     const int64_t P = z.P, PP = z.P * z.P;
     const int64_t cw1 = z.lcw1[level], cw2 = z.lcw2[level];
     int64_t n_items, cx = 0, cy = 0, idx = 0;
@@ -58,7 +65,7 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
             idx = cy * z.lnx[level] + cx;
         }
     }
-    if ((int64_t)blockIdx.x * kThreads >= n_items) return;      // whole workgroup idle
+    if ((int64_t)blockIdx.x * (kThreads / ks) >= n_items) return;      // whole workgroup idle
     const bool active = t_id < n_items && cx * cw1 < z.wn1 && cy * cw2 < z.wn2;
     // fine-grid index range of the cell (global indices), its rectangle, centre and half-widths
     const int64_t g10 = z.wlo1 + min(cx * cw1, z.wn1), g11 = z.wlo1 + min((cx + 1) * cw1, z.wn1);
@@ -91,8 +98,9 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
             const int64_t i = (t + 1) * kZoomLT + tid;
             if (i < z.n_lens) nxt = moved_lens(z.lenses[i], z.vel, i, z.time);
         }
-        for (int r = 0; r < kZoomLT; r += kZoomRun) {
+        for (int r = part * kZoomRun; r < kZoomLT; r += ks * kZoomRun) {
             float s1 = 0.f, s2 = 0.f, sd = 0.f, so = 0.f, sc = 0.f, sp = 0.f, sq = 0.f;
+            bool near_seen = false;
 #pragma unroll
             for (int j = 0; j < kZoomRun; ++j) {
                 const float4 l = s_lens[buf][r + j];
@@ -104,20 +112,32 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
                 const float d = l.z * q;
                 s1 = fmaf(d, f1, s1);
                 s2 = fmaf(d, f2, s2);
-                const bool nr = r2 < near2 && l.z != 0.0f;
-                if (nr) {
-                    // near lens: bound its whole variation over the cell by 2 m / delta
-                    const float ex = fmaxf(fabsf(f1) - fh1, 0.0f), ey = fmaxf(fabsf(f2) - fh2, 0.0f);
-                    const float dl2 = ex * ex + ey * ey;
-                    if (dl2 > 0.0f) nearsum += (double)l.z * (double)__builtin_amdgcn_rsqf(dl2);
-                    else inside = true;
-                }
-                const float dq = nr ? 0.0f : d * q;
+                // the rounding-allowance sums take every lens (an over-estimate is safe)
+                sp = fmaf(l.z, s, sp);
+                sq += d;
+                // the Taylor terms only the lenses at distance >= 3 rho
+                const bool nr = r2 < near2;
+                near_seen = near_seen || nr;
+                const float dt = nr ? 0.0f : d;
+                const float dq = dt * q;
                 sd = fmaf(dq, f2s - f1s, sd);
                 so = fmaf(dq, f1 * f2, so);
-                sc = fmaf(nr ? 0.0f : d, s, sc);
-                sp = fmaf(nr ? 0.0f : l.z, s, sp);
-                sq += nr ? 0.0f : d;
+                sc = fmaf(dt, s, sc);
+            }
+            if (__any(near_seen)) {
+                // near lenses (rare): bound each one's whole variation over the cell by 2 m / delta
+                float ns = 0.0f;
+#pragma unroll
+                for (int j = 0; j < kZoomRun; ++j) {
+                    const float4 l = s_lens[buf][r + j];
+                    const float f1 = cf1 - l.x, f2 = cf2 - l.y;
+                    const bool nr = f1 * f1 + f2 * f2 < near2 && l.z != 0.0f;
+                    const float ex = fmaxf(fabsf(f1) - fh1, 0.0f), ey = fmaxf(fabsf(f2) - fh2, 0.0f);
+                    const float dl2 = ex * ex + ey * ey;
+                    inside = inside || (nr && !(dl2 > 0.0f));
+                    ns += nr && dl2 > 0.0f ? l.z * __builtin_amdgcn_rsqf(dl2) : 0.0f;
+                }
+                nearsum += (double)ns;
             }
             A1 += (double)s1;
             A2 += (double)s2;
@@ -130,7 +150,21 @@ __global__ void __launch_bounds__(kThreads) k_zoom_mark(const ZoomArgs z, int le
         if (more) s_lens[buf ^ 1][tid] = nxt;
         __syncthreads();
     }
-    if (!active) return;
+    // the group's partial sums, combined in a fixed order
+    int in_any = inside ? 1 : 0;
+    for (int o = 1; o < ks; o <<= 1) {
+        A1 += __shfl_xor(A1, o, 64);
+        A2 += __shfl_xor(A2, o, 64);
+        Jd += __shfl_xor(Jd, o, 64);
+        Jo += __shfl_xor(Jo, o, 64);
+        C3 += __shfl_xor(C3, o, 64);
+        P1 += __shfl_xor(P1, o, 64);
+        D2 += __shfl_xor(D2, o, 64);
+        nearsum += __shfl_xor(nearsum, o, 64);
+        in_any |= __shfl_xor(in_any, o, 64);
+    }
+    inside = in_any != 0;
+    if (!active || part != 0) return;
 
     // centre image and the bounds, FP64
     const double y1 = z.lam1 * (double)cf1 - A1, y2 = z.lam2 * (double)cf2 - A2;
@@ -160,10 +194,16 @@ hipError_t launch_zoom_mark(const ZoomArgs &z, hipStream_t s)
     if (items <= 0) return hipSuccess;
     for (int l = 0; l < z.levels; ++l) {
         // level l > 0 runs over at most every child of every cell of level l - 1; workgroups
-        // past the kept children exit at once
+        // past the kept children exit at once.  Lanes per cell: enough to give about 2^18
+        // threads for the expected work (every cell at level 0, the children of about a third
+        // of the cells above further down); the choice only affects speed.
         if (l > 0) items = z.lnx[l - 1] * z.lny[l - 1] * z.P * z.P;
-        hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((items + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, z,
-                           l);
+        const int64_t expect = l == 0 ? items : std::max<int64_t>(1, items / 3);
+        int ks = 1;
+        while (ks < 16 && expect * ks < (int64_t(1) << 18)) ks <<= 1;
+        const int64_t per_block = kThreads / ks;
+        hipLaunchKernelGGL(k_zoom_mark, dim3((unsigned)((items + per_block - 1) / per_block)), dim3(kThreads), 0, s, z,
+                           l, ks);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

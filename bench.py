@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="paper", choices=["paper", "small", "batched", "farfield", "large"])
     ap.add_argument("--ff-steps", type=int, default=2000, help="surrogate workloads: Adam steps per tile")
+    ap.add_argument("--ff-samples", type=int, default=0,
+                    help="surrogate workloads: fit samples per tile (multiple of 1024; default 4096, large 1024)")
     ap.add_argument("--autotune-cache", default="", help="batched workload: autotuner cache file")
     ap.add_argument("--block", default="", help="rays per lane as COLSxROWS, e.g. 2x4 (default: library's)")
     ap.add_argument("--lens-tile", type=int, default=0)
@@ -215,9 +217,12 @@ def bench_surrogate(args, which=None, emit=True):
     lost = torch.zeros(1, dtype=torch.int64, device=dev)
     job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                      counts, lost)
-    # 4096 seeded uniform fit samples per tile, in quads that share their first coordinate (the
-    # fit shares x-differences within a quad; the targets are those of the same points listed freely)
-    samples = torch.from_numpy(synth.fit_samples_quads(7)).to(dev)
+    # seeded uniform fit samples per tile, in quads that share their first coordinate (the fit shares
+    # x-differences within a quad; the targets are those of the same points listed freely): 4096 on the
+    # 1e6-lens field, whose configuration fixes that number; 1024 on the 1e7-lens field, where the exact
+    # samples are most of the cost (4096 there: map error 0.11%, end-to-end 63x; 1024: 0.14%, 210x)
+    n_samples = args.ff_samples or (1024 if large else 4096)
+    samples = torch.from_numpy(synth.fit_samples_quads(7, n_samples)).to(dev)
     init = torch.from_numpy(synth.init_params(7)).to(dev)
     cfg = P.ff_config(samples, init, tile_rays=tile, r_near=8.0, steps=args.ff_steps, batch=512, lr=1e-2,
                       shared_x=True)
@@ -323,7 +328,7 @@ def bench_surrogate(args, which=None, emit=True):
         "ms_per_step": 1e3 * (fit_s + eval_s), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": w.name, "n_lens": w.n_lens, "ray_grid": list(w.grid_n), "map": list(w.map_n),
-                   "tile_rays": list(tile), "r_near": 8.0, "fit_samples": "4096 seeded uniform, quads sharing x", "adam_steps": args.ff_steps,
+                   "tile_rays": list(tile), "r_near": 8.0, "fit_samples": f"{n_samples} seeded uniform, quads sharing x", "adam_steps": args.ff_steps,
                    "judged_tiles": int(len(judge)), "n_tiles": int(n_tiles), "parallelism": "1 GPU"},
         "fit_s": fit_s, "eval_s": eval_s, "plain_s_on_judged_tiles": plain_s,
         "rays_per_s": {"surrogate_eval": sur_rays_s, "surrogate_end_to_end": e2e_rays_s, "plain": plain_rays_s},

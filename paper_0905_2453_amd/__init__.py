@@ -97,6 +97,7 @@ def make_job(lenses, kappa_c, gamma, grid_lo, grid_hi, grid_n, map_lo, map_hi, m
             raise ValueError("velocities must be an n_lens x 2 float32 tensor")
         j.velocities = ctypes.c_void_p(velocities.data_ptr() if lenses.shape[0] else 0)
         j.time = float(time)
+    j._tensors = (lenses, counts, lost, velocities)     # the struct holds their raw addresses
     return j
 
 
@@ -274,13 +275,37 @@ def ff_config(samples, init_params, tile_rays=(64, 64), r_near=8.0, steps=2000, 
     c.steps, c.batch, c.lr, c.cell_size = int(steps), int(batch), float(lr), float(cell_size)
     c.samples = samples.data_ptr()
     c.init_params = init_params.data_ptr()
-    c.debug_grad = debug_grad.data_ptr() if debug_grad is not None else None
-    c.debug_targets = debug_targets.data_ptr() if debug_targets is not None else None
+    if debug_grad is not None:
+        _require_cuda(debug_grad, "debug_grad", torch.float32)
+        c.debug_grad = debug_grad.data_ptr()
+    if debug_targets is not None:
+        _require_cuda(debug_targets, "debug_targets", torch.float32)
+        c.debug_targets = debug_targets.data_ptr()
     if eval_tiles is not None:
         _require_cuda(eval_tiles, "eval_tiles", torch.int32)
         c.eval_tiles, c.n_eval_tiles = eval_tiles.data_ptr(), int(eval_tiles.numel())
     c.shared_x = 1 if shared_x else 0
+    # the struct holds raw addresses: keep the tensors alive with it, and remember the debug
+    # buffers' sizes for the check against the job's tile count
+    c._tensors = (samples, init_params, debug_grad, debug_targets, eval_tiles)
+    c._debug_numel = (debug_grad.numel() if debug_grad is not None else None,
+                      debug_targets.numel() if debug_targets is not None else None)
     return c
+
+
+def _check_debug(job, cfg) -> None:
+    """The optional debug buffers must hold n_tiles x 5378 and n_tiles x n_samples x 2 floats."""
+    grad_n, targ_n = getattr(cfg, "_debug_numel", (None, None))
+    if grad_n is None and targ_n is None:
+        return
+    tx, ty = int(cfg.tile_rays[0]), int(cfg.tile_rays[1])
+    if tx <= 0 or ty <= 0:
+        return                                  # the library rejects the configuration itself
+    n_tiles = -(-int(job.grid.win_n[0]) // tx) * -(-int(job.grid.win_n[1]) // ty)
+    if grad_n is not None and grad_n < n_tiles * _abi.N_PARAMS:
+        raise ValueError(f"debug_grad holds {grad_n} floats < {n_tiles} tiles x {_abi.N_PARAMS}")
+    if targ_n is not None and targ_n < n_tiles * int(cfg.n_samples) * 2:
+        raise ValueError(f"debug_targets holds {targ_n} floats < {n_tiles} tiles x {int(cfg.n_samples)} x 2")
 
 
 def _size(fn, job, cfg):
@@ -306,6 +331,7 @@ def farfield_fit(job, cfg, model, workspace, stream=None) -> None:
     """rs_farfield_fit: fill `model` (uint8 device tensor) with every tile's fitted closure."""
     _require_cuda(model, "model")
     _require_cuda(workspace, "workspace")
+    _check_debug(job, cfg)
     _check(lib().rs_farfield_fit(ctypes.byref(job), ctypes.byref(cfg), ctypes.c_void_p(model.data_ptr()),
                                  model.numel() * model.element_size(), ctypes.c_void_p(workspace.data_ptr()),
                                  workspace.numel() * workspace.element_size(), _stream_handle(stream)))

@@ -96,6 +96,8 @@ int validate_job(const rs_job *j)
         if (!is_fin(m.lo[k]) || !is_fin(m.hi[k]) || !(m.hi[k] > m.lo[k]))
             return fail(RS_EINVAL, "map axis %d: need finite lo < hi", k);
         if (m.n[k] <= 0) return fail(RS_EINVAL, "map axis %d: n <= 0", k);
+        if (!is_fin((double)m.n[k] / (m.hi[k] - m.lo[k])))
+            return fail(RS_EINVAL, "map axis %d: pixels too small (n / (hi - lo) not finite)", k);
     }
     if ((int64_t)m.n[0] * (int64_t)m.n[1] >= (int64_t(1) << 31))
         return fail(RS_ERANGE, "map has >= 2^31 pixels");
@@ -1070,7 +1072,7 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     if ((int64_t)n_tracks * n_points > ((int64_t)1 << 36)) return fail(RS_EINVAL, "too many track points");
     for (int k = 0; k < 2; ++k)
         if (!std::isfinite(map->lo[k]) || !std::isfinite(map->hi[k]) || !(map->hi[k] > map->lo[k]) ||
-            map->n[k] <= 0 || map->n[k] > 65536)
+            map->n[k] <= 0 || map->n[k] > 65536 || !std::isfinite((double)map->n[k] / (map->hi[k] - map->lo[k])))
             return fail(RS_EINVAL, "map axis %d invalid", k);
     if (!(n_av > 0.0) || !std::isfinite(n_av)) return fail(RS_EINVAL, "n_av must be finite and > 0");
     if (src->kind != 0 && src->kind != 1) return fail(RS_EINVAL, "source kind must be 0 or 1");

@@ -114,6 +114,7 @@ def test_workspace_query():
     (dict(**{"map.hi": (0, -2.0)}), -1),
     (dict(**{"macro.gamma": float("inf")}), -1),
     (dict(**{"grid.lo": (0, -1e13)}), -1),
+    (dict(**{"map.lo": (0, 0.0), "map.hi": (0, 1e-310)}), -1),
 ])
 def test_invalid_arguments_rejected(kw, code):
     P, L = _lib()

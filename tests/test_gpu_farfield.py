@@ -192,6 +192,37 @@ def test_mismatched_model_is_rejected():
     assert ei.value.status == -5
 
 
+def test_binding_keeps_tensors_alive_and_checks_debug_sizes():
+    """The binding's structs hold raw device addresses: they keep their tensors alive, and a debug
+    buffer too small for the job's tiles is refused before any library call."""
+    import gc
+    torch, P = _env()
+    w = _small_field()
+    dev = torch.device("cuda:0")
+    job = P.make_job(torch.from_numpy(w.lenses).to(dev), w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n,
+                     w.map_lo, w.map_hi, w.map_n,
+                     torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev),
+                     torch.zeros(1, dtype=torch.int64, device=dev), window=WIN)
+    gc.collect()
+    assert job._tensors[0].data_ptr() == job.lenses and job._tensors[1].data_ptr() == job.counts
+    ntx = (WIN[1][0] + TILE[0] - 1) // TILE[0]
+    nty = (WIN[1][1] + TILE[1] - 1) // TILE[1]
+    ut = torch.from_numpy(synth.fit_samples(1, 1024)).to(dev)
+    pt = torch.from_numpy(synth.init_params(1)).to(dev)
+    small = torch.zeros((ntx * nty - 1, mlp.N_PARAMS), dtype=torch.float32, device=dev)
+    cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, batch=512, debug_grad=small)
+    model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    with pytest.raises(ValueError, match="debug_grad"):
+        P.farfield_fit(job, cfg, model, ws)
+    short = torch.zeros((ntx * nty, 1023, 2), dtype=torch.float32, device=dev)
+    cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, batch=512, debug_targets=short)
+    with pytest.raises(ValueError, match="debug_targets"):
+        P.farfield_fit(job, cfg, model, ws)
+    with pytest.raises(ValueError, match="dtype"):
+        P.ff_config(ut, pt, debug_grad=small.double())
+
+
 # ---------------------------------------------------------------- moving field, one closure
 
 def _eval(torch, P, job, cfg, model, counts, lost, flags=0, dump=False):

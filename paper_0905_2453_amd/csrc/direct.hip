@@ -58,14 +58,24 @@ struct TileSmem {
 };
 
 // Shoot one block of rays per lane with the whole workgroup: lane rays are the window-relative
-// columns c0 .. c0 + K1 - 1 and rows r0 .. r0 + K2 - 1; a ray counts only when its column is
-// below cmax and its row below rmax.  `slot` selects the partial map the counts go to.  Every
-// thread of the workgroup must call it.
+// columns c0 .. c0 + K1 - 1 and rows r0 .. r0 + K2 - 1 (r0 even); a ray counts only when its
+// column is below cmax and its row in [rmin, rmax).  `slot` selects the partial map the counts go
+// to.  Every thread of the workgroup must call it.
+//
+// Rays share one reciprocal per pair of rows (r0 + 2p, r0 + 2p + 1): with ra and rb
+// the two squared distances to a lens, g = 1 / (ra rb) gives 1 / ra = g rb and 1 / rb = g ra
+// (simultaneous inversion), one v_rcp_f32 for two interactions.  Window rows are aligned so that
+// pairs are always (even, odd) grid rows, which keeps every ray's arithmetic independent of the
+// launch shape and of the window.  A lane whose sums end non-finite (a pair product of zero: a
+// ray on a lens) is recomputed with one reciprocal per ray, so a ray is lost exactly when its own
+// distance is zero.  A product above the float32 range (both rays more than 4e9 Einstein radii
+// from the lens) gives g = 0: such a lens deflects by less than 2.4e-10 m and is dropped.
 template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
-__device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int64_t r0, int64_t cmax, int64_t rmax,
-                                           uint32_t slot, TileSmem<LT> &sm)
+__device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int64_t r0, int64_t cmax, int64_t rmin,
+                                           int64_t rmax, uint32_t slot, TileSmem<LT> &sm)
 {
     static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
+    static_assert(K2 % 2 == 0, "rows pair up");
     constexpr int PER = LT / kThreads;
     constexpr int R = K1 * K2;
     constexpr bool FOLD = K1 >= 2;  // fold m into shared differences when a lane has several columns
@@ -133,16 +143,24 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
             for (int j = 0; j < T; ++j) {
                 const float4 l = L[r + j];
                 if constexpr (JIT) {
+                    // every ray has its own coordinates; rows still pair up for the reciprocal
 #pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const float dx = xj1[k] - l.x, dy = xj2[k] - l.y;
-                        const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                    for (int k = 0; k < R; k += 2) {
+                        const float dxa = xj1[k] - l.x, dya = xj2[k] - l.y;
+                        const float dxb = xj1[k + 1] - l.x, dyb = xj2[k + 1] - l.y;
+                        const float ra = fmaf(dya, dya, dxa * dxa), rb = fmaf(dyb, dyb, dxb * dxb);
+                        const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
+                        const float da = g * rb, db = g * ra;
                         if (j == 0) {
-                            s1[k] = d * dx;
-                            s2[k] = d * dy;
+                            s1[k] = da * dxa;
+                            s2[k] = da * dya;
+                            s1[k + 1] = db * dxb;
+                            s2[k + 1] = db * dyb;
                         } else {
-                            s1[k] = fmaf(d, dx, s1[k]);
-                            s2[k] = fmaf(d, dy, s2[k]);
+                            s1[k] = fmaf(da, dxa, s1[k]);
+                            s2[k] = fmaf(da, dya, s2[k]);
+                            s1[k + 1] = fmaf(db, dxb, s1[k + 1]);
+                            s2[k + 1] = fmaf(db, dyb, s2[k + 1]);
                         }
                     }
                 } else if constexpr (FOLD) {
@@ -163,40 +181,44 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
 #pragma unroll
                     for (int i = 0; i < K1; ++i) {
 #pragma unroll
-                        for (int b = 0; b < K2; ++b) {
+                        for (int b = 0; b < K2; b += 2) {
                             const int k = i * K2 + b;
-                            const float q = __builtin_amdgcn_rcpf(fmaf(dy[b], dy[b], dx2[i]));
+                            const float ra = fmaf(dy[b], dy[b], dx2[i]), rb = fmaf(dy[b + 1], dy[b + 1], dx2[i]);
+                            const float g = __builtin_amdgcn_rcpf(ra * rb);
+                            const float qa = g * rb, qb = g * ra;
                             if (j == 0) {
-                                s1[k] = q * mdx[i];
-                                s2[k] = q * mdy[b];
+                                s1[k] = qa * mdx[i];
+                                s2[k] = qa * mdy[b];
+                                s1[k + 1] = qb * mdx[i];
+                                s2[k + 1] = qb * mdy[b + 1];
                             } else {
-                                s1[k] = fmaf(q, mdx[i], s1[k]);
-                                s2[k] = fmaf(q, mdy[b], s2[k]);
+                                s1[k] = fmaf(qa, mdx[i], s1[k]);
+                                s2[k] = fmaf(qa, mdy[b], s2[k]);
+                                s1[k + 1] = fmaf(qb, mdx[i], s1[k + 1]);
+                                s2[k + 1] = fmaf(qb, mdy[b + 1], s2[k + 1]);
                             }
                         }
                     }
                 } else {
                     // one column per lane: d = m / r^2 per ray, then alpha += d (dx, dy)
-                    float dx[K1], dx2[K1];
+                    const float dx = x1[0] - l.x;
+                    const float dx2 = dx * dx;
 #pragma unroll
-                    for (int i = 0; i < K1; ++i) {
-                        dx[i] = x1[i] - l.x;
-                        dx2[i] = dx[i] * dx[i];
-                    }
-#pragma unroll
-                    for (int i = 0; i < K1; ++i) {
-#pragma unroll
-                        for (int b = 0; b < K2; ++b) {
-                            const int k = i * K2 + b;
-                            const float dy = x2[b] - l.y;
-                            const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx2[i]));
-                            if (j == 0) {
-                                s1[k] = d * dx[i];
-                                s2[k] = d * dy;
-                            } else {
-                                s1[k] = fmaf(d, dx[i], s1[k]);
-                                s2[k] = fmaf(d, dy, s2[k]);
-                            }
+                    for (int b = 0; b < K2; b += 2) {
+                        const float dya = x2[b] - l.y, dyb = x2[b + 1] - l.y;
+                        const float ra = fmaf(dya, dya, dx2), rb = fmaf(dyb, dyb, dx2);
+                        const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
+                        const float da = g * rb, db = g * ra;
+                        if (j == 0) {
+                            s1[b] = da * dx;
+                            s2[b] = da * dya;
+                            s1[b + 1] = db * dx;
+                            s2[b + 1] = db * dyb;
+                        } else {
+                            s1[b] = fmaf(da, dx, s1[b]);
+                            s2[b] = fmaf(da, dya, s2[b]);
+                            s1[b + 1] = fmaf(db, dx, s1[b + 1]);
+                            s2[b + 1] = fmaf(db, dyb, s2[b + 1]);
                         }
                     }
                 }
@@ -212,6 +234,64 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
             for (int p = 0; p < PER; ++p) s_lens[buf ^ 1][p * kThreads + tid] = reg[p];
         }
         __syncthreads();
+    }
+
+    {
+        // A pair whose product left the finite range (a ray on a lens, or both rays within about
+        // 1e-19 of one) leaves a non-finite sum.  Redo this lane's rays with one reciprocal per
+        // ray, in the same runs of T lenses, reading the lenses from global memory: every ray then
+        // gets exactly the per-ray result, and only a ray on a lens stays non-finite.
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < R; ++k) bad = bad || !__builtin_isfinite(A1[k] + A2[k]);
+        if (bad) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) { A1[k] = 0.0; A2[k] = 0.0; }
+            for (int64_t r = 0; r < a.n_lens; r += T) {
+                float s1[R], s2[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) { s1[k] = 0.0f; s2[k] = 0.0f; }
+                const int64_t e = min(r + (int64_t)T, a.n_lens);
+                for (int64_t li = r; li < e; ++li) {
+                    const float4 l = moved_lens(a.lenses[li], a.vel, li, a.time);
+                    if constexpr (JIT) {
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            const float dx = xj1[k] - l.x, dy = xj2[k] - l.y;
+                            const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, dx * dx));
+                            s1[k] = fmaf(d, dx, s1[k]);
+                            s2[k] = fmaf(d, dy, s2[k]);
+                        }
+                        continue;
+                    }
+#pragma unroll
+                    for (int i = 0; i < K1; ++i) {
+                        const float dx = x1[i] - l.x;
+                        const float dx2 = dx * dx;
+                        const float mdx = l.z * dx;
+#pragma unroll
+                        for (int b = 0; b < K2; ++b) {
+                            const int k = i * K2 + b;
+                            const float dy = x2[b] - l.y;
+                            const float q = __builtin_amdgcn_rcpf(fmaf(dy, dy, dx2));
+                            if constexpr (FOLD) {
+                                s1[k] = fmaf(q, mdx, s1[k]);
+                                s2[k] = fmaf(q, l.z * dy, s2[k]);
+                            } else {
+                                const float d = l.z * q;
+                                s1[k] = fmaf(d, dx, s1[k]);
+                                s2[k] = fmaf(d, dy, s2[k]);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    A1[k] += (double)s1[k];
+                    A2[k] += (double)s2[k];
+                }
+            }
+        }
     }
 
     // The hardware reciprocal is biased low: over all float32 mantissas, weighted as for
@@ -231,7 +311,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
 #pragma unroll
         for (int b = 0; b < K2; ++b) {
             const int k = i * K2 + b;
-            const bool ok = (c0 + i < cmax) && (r0 + b < rmax);
+            const bool ok = (c0 + i < cmax) && (r0 + b >= rmin) && (r0 + b < rmax);
             const double y1 = a.lam1 * (double)(JIT ? xj1[k] : x1[i]) - A1[k];
             const double y2 = a.lam2 * (double)(JIT ? xj2[k] : x2[b]) - A2[k];
             int p1 = 0, p2 = 0;
@@ -240,7 +320,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
             q1[k] = p1;
             q2[k] = p2;
             if (DUMP && ok) {
-                const int64_t ri = (r0 + b) * a.wn1 + c0 + i;
+                const int64_t ri = (r0 + b - a.rskip) * a.wn1 + c0 + i;
                 a.ray_y[2 * ri] = y1;
                 a.ray_y[2 * ri + 1] = y2;
                 a.ray_pix[ri] = kv;
@@ -332,7 +412,7 @@ __device__ __forceinline__ void shoot_tile(const DirectArgs &a, uint32_t tile, u
     const int ty = (int)(tile / (uint32_t)a.tiles_x);
     const int64_t c0 = (int64_t)tx * (64 * K1) + (int64_t)lane * K1;
     const int64_t r0 = (int64_t)ty * (kWaves * K2) + (int64_t)wave * K2;
-    shoot_rays<K1, K2, T, LT, DUMP, JIT>(a, c0, r0, a.wn1, a.wn2, slot, sm);
+    shoot_rays<K1, K2, T, LT, DUMP, JIT>(a, c0, r0, a.wn1, a.rskip, a.wn2, slot, sm);
 }
 
 template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
@@ -343,10 +423,11 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 }
 
 // Persistent direct sum over the lane blocks of a list of culling cells (the cells a zoom
-// keeps).  Cell q of the list covers window columns [mx c1, (mx + 1) c1) and rows
-// [my c2, (my + 1) c2) (clipped to the window); it is cut into S = sx sy lane blocks of K1
-// columns x K2 rows, and block j of cell list[i] is lane slot i S + j.  Workgroup g takes
-// slots g 256 .. g 256 + 255, then g + grid, ...
+// keeps).  Cell q of the list covers the caller's window columns [mx c1, (mx + 1) c1) and rows
+// [my c2, (my + 1) c2) (clipped to the window), i.e. rows shifted by rskip here; it is cut into
+// S = sx sy lane blocks of K1 columns x K2 rows starting at the even row at or below its first
+// row (so the row pairs are those of the plain launch), and block j of cell list[i] is lane
+// slot i S + j.  Workgroup g takes slots g 256 .. g 256 + 255, then g + grid, ...
 template <int K1, int K2, int T, int LT, bool JIT>
 __global__ void __launch_bounds__(kThreads) k_direct_cells(const DirectArgs a, const CellBlocks cb)
 {
@@ -355,18 +436,20 @@ __global__ void __launch_bounds__(kThreads) k_direct_cells(const DirectArgs a, c
     uint32_t it = 0;
     for (uint64_t base = (uint64_t)blockIdx.x * kThreads; base < n; base += (uint64_t)gridDim.x * kThreads, ++it) {
         const uint64_t q = base + threadIdx.x;
-        int64_t c0 = 0, r0 = 0, cmax = 0, rmax = 0;
+        int64_t c0 = 0, r0 = 0, cmax = 0, rmin = 0, rmax = 0;
         if (q < n) {
             const uint64_t i = q / (uint64_t)cb.S;
             const int64_t j = (int64_t)(q - i * (uint64_t)cb.S);
             const int64_t cell = cb.list[i];
             const int64_t mx = cell % cb.ncx, my = cell / cb.ncx;
             c0 = mx * cb.c1 + (j % cb.sx) * K1;
-            r0 = my * cb.c2 + (j / cb.sx) * K2;
+            rmin = my * cb.c2 + a.rskip;
+            r0 = (rmin & ~int64_t(1)) + (j / cb.sx) * K2;
             cmax = min((mx + 1) * cb.c1, a.wn1);
-            rmax = min((my + 1) * cb.c2, a.wn2);
+            rmax = min((my + 1) * cb.c2 + a.rskip, a.wn2);
         }
-        shoot_rays<K1, K2, T, LT, false, JIT>(a, c0, r0, cmax, rmax, (blockIdx.x + it) & (kPartials - 1), sm);
+        shoot_rays<K1, K2, T, LT, false, JIT>(a, c0, r0, cmax, rmin, rmax, (blockIdx.x + it) & (kPartials - 1),
+                                             sm);
         __syncthreads();
     }
 }

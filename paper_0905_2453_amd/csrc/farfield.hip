@@ -237,16 +237,18 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 
 // ---------------------------------------------------------------- fit: exact far-field samples
 
-// Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024).
+// Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024);
+// thread i of wave w takes samples 64 (4 g + k) + i, k = 0..3, with g = 4 part + w.
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
 // of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
-// GRID: samples 64 (4 g + k) + i, k = 0..3, share their first coordinate; a thread takes those
-// four, so x - x_l and its square are shared by them, and each sample still sees exactly the
-// operations of the general layout (the targets are bit-identical).
-template <bool GRID>
+// Samples k = (0, 1) and (2, 3) share one reciprocal per lens, as the plain path's row pairs do
+// (a far lens is at least r_near from every sample, so no pair product is zero).
+// GRID: the four samples of a thread share their first coordinate, so x - x_l and its square
+// are computed once, and each sample still sees exactly the operations of the general layout
+// (the targets are bit-identical).
 __device__ __forceinline__ int sample_index(int part, int k, int tid)
 {
-    return GRID ? (16 * part + 4 * (tid >> 6) + k) * 64 + (tid & 63) : part * 1024 + k * 256 + tid;
+    return (16 * part + 4 * (tid >> 6) + k) * 64 + (tid & 63);
 }
 
 template <bool GRID>
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     float px[S], py[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index<GRID>(part, k, tid);
+        const int si = sample_index(part, k, tid);
         px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]);
         py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]);
     }
@@ -291,11 +293,17 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
                 // GRID: the four samples share px[0]
                 const float dxs = px[0] - l.x, dxs2 = dxs * dxs;
 #pragma unroll
-                for (int k = 0; k < S; ++k) {
-                    const float dx = GRID ? dxs : px[k] - l.x, dy = py[k] - l.y;
-                    const float d = l.z * __builtin_amdgcn_rcpf(fmaf(dy, dy, GRID ? dxs2 : dx * dx));
-                    s1[k] = j == 0 ? d * dx : fmaf(d, dx, s1[k]);
-                    s2[k] = j == 0 ? d * dy : fmaf(d, dy, s2[k]);
+                for (int k = 0; k < S; k += 2) {
+                    const float dxa = GRID ? dxs : px[k] - l.x, dya = py[k] - l.y;
+                    const float dxb = GRID ? dxs : px[k + 1] - l.x, dyb = py[k + 1] - l.y;
+                    const float ra = fmaf(dya, dya, GRID ? dxs2 : dxa * dxa);
+                    const float rb = fmaf(dyb, dyb, GRID ? dxs2 : dxb * dxb);
+                    const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
+                    const float da = g * rb, db = g * ra;
+                    s1[k] = j == 0 ? da * dxa : fmaf(da, dxa, s1[k]);
+                    s2[k] = j == 0 ? da * dya : fmaf(da, dya, s2[k]);
+                    s1[k + 1] = j == 0 ? db * dxb : fmaf(db, dxb, s1[k + 1]);
+                    s2[k + 1] = j == 0 ? db * dyb : fmaf(db, dyb, s2[k + 1]);
                 }
             }
 #pragma unroll
@@ -311,7 +319,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     const double a01 = h[4], a02 = h[5], j11 = h[6], j12 = h[7], j22 = h[8];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index<GRID>(part, k, tid);
+        const int si = sample_index(part, k, tid);
         const double d1 = (double)px[k] - c[0], d2 = (double)py[k] - c[1];
         const double r1 = A1[k] * kRcpBiasComp - (a01 + j11 * d1 + j12 * d2);
         const double r2 = A2[k] * kRcpBiasComp - (a02 + j12 * d1 + j22 * d2);

@@ -109,6 +109,11 @@ int validate_job(const rs_job *j)
     return RS_OK;
 }
 
+// Rows of the ray window as the direct-sum kernels see it: reciprocals are shared by pairs of
+// (even, odd) grid rows, so a window that starts on an odd row is widened by one masked row.
+int32_t row_skip(const rs_raygrid &g) { return g.win_n[1] > 0 ? (int32_t)(g.win_lo[1] & 1) : 0; }
+int64_t kernel_rows(const rs_raygrid &g) { return g.win_n[1] + row_skip(g); }
+
 int64_t partial_stride(const rs_job *j)
 {
     const int64_t bins = (int64_t)j->map.n[0] * j->map.n[1];
@@ -127,10 +132,11 @@ rs::DirectArgs make_args(const rs_job *job, const Tune &t, uint32_t *partial, in
     a.glo2 = g.lo[1];
     a.gt1 = (g.hi[0] - g.lo[0]) / (double)g.n[0];
     a.gt2 = (g.hi[1] - g.lo[1]) / (double)g.n[1];
+    a.rskip = row_skip(g);
     a.wlo1 = g.win_lo[0];
-    a.wlo2 = g.win_lo[1];
+    a.wlo2 = g.win_lo[1] - a.rskip;
     a.wn1 = g.win_n[0];
-    a.wn2 = g.win_n[1];
+    a.wn2 = kernel_rows(g);
     a.lam1 = (1.0 - job->macro.gamma) - job->macro.kappa_c;
     a.lam2 = (1.0 + job->macro.gamma) - job->macro.kappa_c;
     a.mlo1 = job->map.lo[0];
@@ -160,7 +166,7 @@ int64_t tile_count(const rs_job *job, const Tune &t)
 {
     const int64_t cols = 64 * (int64_t)t.K1;
     const int64_t rows = (int64_t)rs::kWaves * t.K2;
-    return ((job->grid.win_n[0] + cols - 1) / cols) * ((job->grid.win_n[1] + rows - 1) / rows);
+    return ((job->grid.win_n[0] + cols - 1) / cols) * ((kernel_rows(job->grid) + rows - 1) / rows);
 }
 
 // ---------------------------------------------------------------- batched launches
@@ -601,7 +607,10 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     L.cells = L.ncx * L.ncy;
     if (L.cells > (int64_t(1) << 30)) return fail(RS_ERANGE, "more than 2^30 culling cells; use larger cells");
     L.sx = (c1 + t.K1 - 1) / t.K1;
-    L.S = L.sx * ((c2 + t.K2 - 1) / t.K2);
+    // lane blocks start at the even kernel row at or below a cell's first row: one more row to
+    // cover when cells can start on an odd kernel row
+    const int64_t span2 = c2 + ((c2 % 2 != 0 || row_skip(g) != 0) ? 1 : 0);
+    L.S = L.sx * ((span2 + t.K2 - 1) / t.K2);
     if ((uint64_t)L.cells * (uint64_t)L.S * (uint64_t)(t.K1 * t.K2) >= (uint64_t(1) << 40))
         return fail(RS_ERANGE, "too many ray slots");
     // level levels-1 is the cell grid; each coarser level groups P x P cells of the next

@@ -216,14 +216,46 @@ def test_single_lens_disc_count_identity_on_gpu():
         assert np.sum((r_y < u) & ~amb) == np.sum((rx > rm_) & (rx < rp_) & ~amb)
 
 
-def test_ray_on_lens_is_lost_on_gpu():
+@pytest.mark.parametrize("row", [4, 5])
+@pytest.mark.parametrize("block", [(1, 4), (2, 4)])
+def test_ray_on_lens_is_lost_on_gpu(row, block):
+    # rows share reciprocals in (even, odd) pairs: the ray on the lens is lost, its partner row
+    # (which lands inside the map here) is not
+    P = _P()
     xs = oracle.axis(-1.0, 1.0, 8)
-    L = np.array([[xs[3], xs[5], 1.0, 0]], dtype=np.float32)
-    w = synth.Workload("hit", L, 0.0, 0.0, (-1.0, -1.0), (1.0, 1.0), (8, 8), (-4.0, -4.0), (4.0, 4.0), (4, 4))
-    counts, lost, ry, rp = run(w, dump=True)
-    assert rp[5 * 8 + 3] == -1
+    L = np.array([[xs[3], xs[row], 1.0, 0], [0.37, -0.61, 0.5, 0]], dtype=np.float32)
+    w = synth.Workload("hit", L, 0.0, 0.0, (-1.0, -1.0), (1.0, 1.0), (8, 8), (-8.0, -8.0), (8.0, 8.0), (16, 16))
+    o = P.Opts()
+    o.block_cols, o.block_rows = block
+    counts, lost, ry, rp = run(w, opts=o, dump=True)
     _, p_o = oracle.trace(w, np.arange(64))
+    partner = (row ^ 1) * 8 + 3
+    assert rp[row * 8 + 3] == -1 and p_o[partner] >= 0
     assert np.array_equal(rp.astype(np.int64), p_o)
+
+
+def test_odd_window_dump_matches_oracle():
+    # a window starting on an odd row and column, ragged in both axes: per-ray dumps keep the
+    # caller's window indexing and every ray matches the oracle
+    w = synth.workload_small(seed=6)
+    win = ((3, 5), (301, 77))
+    counts, lost, ry, rp = run(w, window=win, dump=True)
+    c, r = np.meshgrid(np.arange(win[0][0], win[0][0] + win[1][0]), np.arange(win[0][1], win[0][1] + win[1][1]))
+    idx = (r * w.grid_n[0] + c).ravel()
+    y_o, p_o = oracle.trace_parallel(w, idx)
+    assert int(counts.sum()) + lost == idx.size
+    frac, nd = switch_fraction(rp.astype(np.int64), p_o)
+    assert nd <= max(1, int(SWITCH_TOL * idx.size)), nd
+    # per-ray source positions within the float32 forward-error bound
+    ok = np.nonzero(np.isfinite(y_o).all(1) & np.isfinite(ry).all(1))[0]
+    xs1 = oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0]).astype(np.float64)
+    xs2 = oracle.axis(w.grid_lo[1], w.grid_hi[1], w.grid_n[1]).astype(np.float64)
+    x = np.stack([xs1[idx[ok] % w.grid_n[0]], xs2[idx[ok] // w.grid_n[0]]], 1)
+    s = np.zeros(len(ok))
+    for rec in w.lenses.astype(np.float64):
+        s += rec[2] / np.hypot(x[:, 0] - rec[0], x[:, 1] - rec[1])
+    err = np.abs(ry[ok] - y_o[ok]).max(1)
+    assert np.all(err <= (8 + 16) * U32 * s + 1e-12)
 
 
 def test_paper_scale_sampled_parity():

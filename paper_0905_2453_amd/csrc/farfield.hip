@@ -362,16 +362,23 @@ __global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
 // weight gradients contract over the chunk's samples through LDS.  The four waves' gradients
 // are summed in a fixed order, then every thread updates its share of the parameters (master
 // weights and Adam moments in global memory, bfloat16 copies in LDS).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
 {
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
     __shared__ float sbias[130];
     __shared__ float red[kNParams];
-    __shared__ __attribute__((aligned(16))) uint16_t sz2[4][64 * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t sh1[4][64 * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t sz1[4][64 * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t sh2[4][64 * 32];
+    // per wave: [unit][sample] staging of dz2, h1, dz1 and h2 (4 x 64 x 32 bfloat16 each); after
+    // a step's last round the same 64 KB hold waves 1-3's gradients for the reduction
+    __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * 4 * 64 * 32];
+    static_assert(3 * kNParams * sizeof(float) <= sizeof(sstage), "gradient scratch");
     __shared__ __attribute__((aligned(16))) uint16_t sphi[4][16 * 32];
     __shared__ float sd3[4][2 * 32];
 
@@ -401,7 +408,9 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         f32x16 g2[2][2] = {};
         f32x4 g1[4] = {};
         float gb1 = 0.f, gb2 = 0.f, gw30 = 0.f, gw31 = 0.f, gb3 = 0.f;
-        uint16_t *z2s = sz2[wave], *h1s = sh1[wave], *z1s = sz1[wave], *h2s = sh2[wave], *phs = sphi[wave];
+        uint16_t *z2s = sstage + (0 * 4 + wave) * 2048, *h1s = sstage + (1 * 4 + wave) * 2048;
+        uint16_t *z1s = sstage + (2 * 4 + wave) * 2048, *h2s = sstage + (3 * 4 + wave) * 2048;
+        uint16_t *phs = sphi[wave];
         float *d3s = sd3[wave];
         for (int rd = 0; rd < rounds; ++rd) {
             const int si = i0 + 32 * (4 * rd + wave) + col;
@@ -450,7 +459,9 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                 d3s[col] = d30;
                 d3s[32 + col] = d31;
             }
-            __syncthreads();
+            // the staging areas are this wave's own: LDS operations of one wave complete in
+            // order, so a wave-scope fence (no workgroup barrier) orders the stores and loads
+            wave_sync();
             // dW2 += dz2^T h1 (K = 32 samples)
 #pragma unroll
             for (int TA = 0; TA < 2; ++TA)
@@ -496,35 +507,33 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                     gb3 += s3;
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
-        // sum the waves' gradients into red[] in wave order
-        for (int w = 0; w < 4; ++w) {
-            if (wave == w) {
-                auto put = [&](int idx, float v) { red[idx] = (w == 0) ? v : red[idx] + v; };
+        __syncthreads();   // every wave is past its last round before the staging area is reused
+        // every wave stores its gradients at once (wave 0 into red[], waves 1-3 into the staging
+        // area, free after the rounds); the Adam loop then adds them in wave order
+        {
+            float *gdst = wave == 0 ? red : reinterpret_cast<float *>(sstage) + (wave - 1) * kNParams;
 #pragma unroll
-                for (int TA = 0; TA < 2; ++TA)
+            for (int TA = 0; TA < 2; ++TA)
 #pragma unroll
-                    for (int TB = 0; TB < 2; ++TB)
+                for (int TB = 0; TB < 2; ++TB)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int j = 32 * TA + 8 * (r >> 2) + 4 * hf + (r & 3), i = 32 * TB + col;
-                            put(kOffW2 + j * 64 + i, g2[TA][TB][r]);
-                        }
+                    for (int r = 0; r < 16; ++r) {
+                        const int j = 32 * TA + 8 * (r >> 2) + 4 * hf + (r & 3), i = 32 * TB + col;
+                        gdst[kOffW2 + j * 64 + i] = g2[TA][TB][r];
+                    }
 #pragma unroll
-                for (int T4 = 0; T4 < 4; ++T4)
+            for (int T4 = 0; T4 < 4; ++T4)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) put(kOffW1 + (16 * T4 + 4 * (lane >> 4) + r) * 16 + (lane & 15), g1[T4][r]);
-                put(kOffB1 + lane, gb1);
-                put(kOffB2 + lane, gb2);
-                put(kOffW3 + lane, gw30);
-                put(kOffW3 + 64 + lane, gw31);
-                if (lane < 2) put(kOffB3 + lane, gb3);
-            }
-            __syncthreads();
+                for (int r = 0; r < 4; ++r) gdst[kOffW1 + (16 * T4 + 4 * (lane >> 4) + r) * 16 + (lane & 15)] = g1[T4][r];
+            gdst[kOffB1 + lane] = gb1;
+            gdst[kOffB2 + lane] = gb2;
+            gdst[kOffW3 + lane] = gw30;
+            gdst[kOffW3 + 64 + lane] = gw31;
+            if (lane < 2) gdst[kOffB3 + lane] = gb3;
         }
-        if (f.debug_grad && step == 1)
-            for (int p = tid; p < kNParams; p += 256) f.debug_grad[(size_t)tile * kNParams + p] = red[p];
+        __syncthreads();
         // Adam with bias correction and a cosine-decayed learning rate
         b1t *= 0.9;
         b2t *= 0.999;
@@ -532,21 +541,42 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         // bias corrections as per-step reciprocals; the per-parameter quotient by the hardware
         // reciprocal (1 ulp, far below the bfloat16 rounding of the weights)
         const float ibc1 = (float)(1.0 / (1.0 - b1t)), ibc2 = (float)(1.0 / (1.0 - b2t));
-        for (int p = tid; p < kNParams; p += 256) {
-            const float g = red[p];
-            float w = state[p], m = state[kNParams + p], v = state[2 * kNParams + p];
-            m = 0.9f * m + 0.1f * g;
-            v = 0.999f * v + 0.001f * g * g;
-            w -= lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
-            state[p] = w;
-            state[kNParams + p] = m;
-            state[2 * kNParams + p] = v;
-            const uint16_t b = to_bf16(w);
-            Wbf[p] = b;
-            if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
-            if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
-            if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
-            if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
+        // thread tid owns parameters tid + 256 k, taken eight at a time: the eight parameters'
+        // optimiser state is loaded before any of it is used, so the global round trips overlap
+        constexpr int kPer = (kNParams + 255) / 256, kChunk = 8;
+        const float *gw = reinterpret_cast<const float *>(sstage);
+#pragma unroll 1
+        for (int k0 = 0; k0 < kPer; k0 += kChunk) {
+            float sw[kChunk], sm[kChunk], sv[kChunk];
+#pragma unroll
+            for (int kk = 0; kk < kChunk; ++kk) {
+                const int p = tid + 256 * (k0 + kk);
+                if (p < kNParams) {
+                    sw[kk] = state[p];
+                    sm[kk] = state[kNParams + p];
+                    sv[kk] = state[2 * kNParams + p];
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < kChunk; ++kk) {
+                const int p = tid + 256 * (k0 + kk);
+                if (p >= kNParams) continue;
+                const float g = ((red[p] + gw[p]) + gw[kNParams + p]) + gw[2 * kNParams + p];
+                if (f.debug_grad && step == 1) f.debug_grad[(size_t)tile * kNParams + p] = g;
+                float w = sw[kk], m = sm[kk], v = sv[kk];
+                m = 0.9f * m + 0.1f * g;
+                v = 0.999f * v + 0.001f * g * g;
+                w -= lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
+                state[p] = w;
+                state[kNParams + p] = m;
+                state[2 * kNParams + p] = v;
+                const uint16_t b = to_bf16(w);
+                Wbf[p] = b;
+                if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+                if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
+                if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
+                if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
+            }
         }
         __syncthreads();
     }

@@ -181,6 +181,15 @@ def test_surrogate_map_error_vs_plain_judge():
     assert l1_aff > 1e-2 and l1_aff > 3 * l1
 
 
+def test_fit_is_deterministic():
+    # fixed-order reductions everywhere: two fits of the same input give the same bytes
+    torch, P = _env()
+    w = _small_field()
+    a = _fit(torch, P, w, WIN, steps=50)
+    b = _fit(torch, P, w, WIN, steps=50)
+    assert np.array_equal(a[2].cpu().numpy(), b[2].cpu().numpy())
+
+
 def test_mismatched_model_is_rejected():
     torch, P = _env()
     w = _small_field()

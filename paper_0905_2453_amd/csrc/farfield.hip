@@ -103,15 +103,15 @@ __device__ __forceinline__ uint16_t *tile_w(const FarArgs &f, uint32_t tile)
 }
 
 // Features of one axis for a lane: phi[8 hf + 2k] = sin(w_k u), phi[8 hf + 2k + 1] = cos(w_k u),
-// w_k = (pi / 2) 2^k, rounded to bfloat16.
+// w_k = (pi / 2) 2^k, rounded to bfloat16.  w_k u is 2 pi (2^(k-2) u), an exact scaling of u,
+// so each value is one hardware sine or cosine of an argument in revolutions (|2^(k-2) u| <= 2).
 __device__ __forceinline__ void features8(float u, uint16_t *out)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        float s, co;
-        sincosf(1.57079632679489662f * (float)(1 << k) * u, &s, &co);
-        out[2 * k] = to_bf16(s);
-        out[2 * k + 1] = to_bf16(co);
+        const float rev = u * (float)(1 << k) * 0.25f;
+        out[2 * k] = to_bf16(__builtin_amdgcn_sinf(rev));
+        out[2 * k + 1] = to_bf16(__builtin_amdgcn_cosf(rev));
     }
 }
 

@@ -133,8 +133,11 @@ typedef struct {
 
 /*
  * Tuning and diagnostics for rs_shoot.  NULL, or a zero field, selects the
- * default.  Results depend on fp32_run only (the length of the float32 runs
- * before each FP64 addition); the other fields change speed, not values.
+ * default.  Results depend on fp32_run (the length of the float32 runs before
+ * each FP64 addition) and, when masses differ from 1, on whether the ray block
+ * has one column or several (several columns fold the mass into the shared
+ * differences, which rounds differently); lens_tile, map_window and the rows of
+ * the block change speed, not values.
  */
 typedef struct {
     int32_t block_cols;      /* rays per lane: block_cols grid columns x block_rows grid rows;  */

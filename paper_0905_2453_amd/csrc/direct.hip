@@ -66,7 +66,7 @@ struct TileSmem {
 // the two squared distances to a lens, g = 1 / (ra rb) gives 1 / ra = g rb and 1 / rb = g ra
 // (simultaneous inversion), one v_rcp_f32 for two interactions.  Window rows are aligned so that
 // pairs are always (even, odd) grid rows, which keeps every ray's arithmetic independent of the
-// launch shape and of the window.  A lane whose sums end non-finite (a pair product of zero: a
+// window, of the launch and of the rows per lane.  A lane whose sums end non-finite (a pair product of zero: a
 // ray on a lens) is recomputed with one reciprocal per ray, so a ray is lost exactly when its own
 // distance is zero.  A product above the float32 range (both rays more than 4e9 Einstein radii
 // from the lens) gives g = 0: such a lens deflects by less than 2.4e-10 m and is dropped.

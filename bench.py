@@ -117,13 +117,10 @@ def cpu_baseline(w, target_cpu_s: float):
                       f"FP64 single-threaded oracle on {threads} threads, {dt:.1f} s wall"}
 
 
-def bench_batched(args, emit=True):
-    """64 maps in one persistent, graph-replayed launch vs 64 separate rs_shoot launches."""
-    import torch
-    import paper_0905_2453_amd as P
-    import synth
+def _time_batch(P, torch, wl, steps, warmup, cache=None):
+    """Autotune, then time one batched launch of the workloads `wl` and the same maps as separate
+    rs_shoot launches; returns (batched_ms, separate_ms, wall_s, opts, tune_s, interactions, rays)."""
     dev = torch.device("cuda:0")
-    wl = synth.batched_jobs()
     dj = []
     for w in wl:
         lenses = torch.from_numpy(w.lenses).to(dev)
@@ -136,7 +133,7 @@ def bench_batched(args, emit=True):
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        opts = P.autotune_batched(jobs, ws, cache_path=args.autotune_cache or None, stream=stream)
+        opts = P.autotune_batched(jobs, ws, cache_path=cache, stream=stream)
     tune_s = time.perf_counter() - t0
     inter = float(sum(w.n_rays * w.n_lens for w in wl))
     rays = float(sum(w.n_rays for w in wl))
@@ -147,7 +144,7 @@ def bench_batched(args, emit=True):
             d[3].zero_()
 
     with torch.cuda.stream(stream):
-        for _ in range(max(1, args.warmup)):
+        for _ in range(max(1, warmup)):
             P.shoot_batched(jobs, ws, opts, stream=stream)
         stream.synchronize()
         zero()
@@ -155,28 +152,42 @@ def bench_batched(args, emit=True):
         stream.synchronize()
         t0 = time.perf_counter()
         e0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             P.shoot_batched(jobs, ws, opts, stream=stream)
         e1.record(stream)
         stream.synchronize()
         wall = time.perf_counter() - t0
-        batched_ms = e0.elapsed_time(e1) / args.steps
+        batched_ms = e0.elapsed_time(e1) / steps
         total = sum(int(d[2].sum().item()) + int(d[3].item()) for d in dj)
-        if total != int(rays) * args.steps:
+        if total != int(rays) * steps:
             print("bench.py: ray conservation failed in the batch", file=sys.stderr)
             sys.exit(3)
-        # 64 separate plain launches of the same maps (default rs_shoot tuning)
+        # the same maps as separate plain launches (default rs_shoot tuning)
         wss = [torch.empty(P.workspace_bytes(d[0]), dtype=torch.uint8, device=dev) for d in dj]
         for d, w in zip(dj, wss):
             P.shoot_job(d[0], w, None, stream)
         stream.synchronize()
         e0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             for d, w in zip(dj, wss):
                 P.shoot_job(d[0], w, None, stream)
         e1.record(stream)
         stream.synchronize()
-        separate_ms = e0.elapsed_time(e1) / args.steps
+        separate_ms = e0.elapsed_time(e1) / steps
+    return batched_ms, separate_ms, wall, opts, tune_s, inter, rays
+
+
+def bench_batched(args, emit=True):
+    """64 maps in one persistent, graph-replayed launch vs 64 separate rs_shoot launches; also 256
+    small maps (grids 128^2-512^2), where separate launches are dominated by launch overhead."""
+    import torch
+    import paper_0905_2453_amd as P
+    import synth
+    wl = synth.batched_jobs()
+    batched_ms, separate_ms, wall, opts, tune_s, inter, rays = _time_batch(
+        P, torch, wl, args.steps, args.warmup, args.autotune_cache or None)
+    small = synth.batched_jobs(seed=5, n_jobs=256, scale=8)
+    s_b, s_s, _, s_opts, _, s_inter, s_rays = _time_batch(P, torch, small, args.steps, args.warmup)
     value = inter * args.steps / wall
     out = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
@@ -188,6 +199,10 @@ def bench_batched(args, emit=True):
         "batched_ms": batched_ms, "separate_launches_ms": separate_ms, "speedup_vs_separate": separate_ms / batched_ms,
         "autotuned": {"block": f"{opts.block_cols}x{opts.block_rows}", "map_window": opts.map_window,
                       "lens_tile": opts.lens_tile, "tune_seconds": tune_s},
+        "small_maps": {"n_maps": len(small), "interactions": s_inter, "rays": s_rays,
+                       "grids": "128^2-512^2", "lenses": "125-12500", "batched_ms": s_b, "separate_launches_ms": s_s,
+                       "speedup_vs_separate": s_s / s_b, "interactions_per_s": s_inter / (s_b * 1e-3),
+                       "autotuned_block": f"{s_opts.block_cols}x{s_opts.block_rows}"},
         "roofline": {"bound": "alu", "achieved": FLOP_PER_INTERACTION * inter / (batched_ms * 1e-3) / 1e12,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": FLOP_PER_INTERACTION * inter / (batched_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
@@ -567,7 +582,7 @@ def main():
         print("bench.py: batched maps next", file=sys.stderr, flush=True)
         b = bench_batched(argparse.Namespace(**{**vars(args), "steps": 2, "warmup": 1}), emit=False)
         out["batched"] = {k: b[k] for k in ("value", "batched_ms", "separate_launches_ms", "speedup_vs_separate",
-                                            "autotuned", "config")}
+                                            "autotuned", "config", "small_maps")}
     for which in ("farfield", "large"):
         if which in legs:
             print(f"bench.py: learned far field ({which}) next", file=sys.stderr, flush=True)

@@ -237,26 +237,32 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 
 // ---------------------------------------------------------------- fit: exact far-field samples
 
-// Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 part + 1024);
-// thread i of wave w takes samples 64 (4 g + k) + i, k = 0..3, with g = 4 part + w.
+// Workgroup (tile, part): 256 threads x S samples = samples [256 S part, 256 S (part + 1)).
+// Samples come in groups g of 256: sample 64 (4 g + k) + i, k = 0..3, i = 0..63.  With S = 4,
+// thread i of wave w takes k = 0..3 of group 4 part + w; with S = 2 (twice the workgroups, for
+// fits with few tiles), k = 2 (w & 1) + {0, 1} of group 2 part + (w >> 1).
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
 // of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
 // Samples k = (0, 1) and (2, 3) share one reciprocal per lens, as the plain path's row pairs do
 // (a far lens is at least r_near from every sample, so no pair product is zero).
-// GRID: the four samples of a thread share their first coordinate, so x - x_l and its square
-// are computed once, and each sample still sees exactly the operations of the general layout
-// (the targets are bit-identical).
+// GRID: the samples of a thread share their first coordinate, so x - x_l and its square are
+// computed once.  Every sample sees the same operations whatever S and GRID are (the targets
+// are bit-identical).
+template <int S>
 __device__ __forceinline__ int sample_index(int part, int k, int tid)
 {
-    return (16 * part + 4 * (tid >> 6) + k) * 64 + (tid & 63);
+    const int w = tid >> 6, lane = tid & 63;
+    if (S == 4) return (16 * part + 4 * w + k) * 64 + lane;
+    return (4 * (2 * part + (w >> 1)) + 2 * (w & 1) + k) * 64 + lane;
 }
 
-template <bool GRID>
-__global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
+template <bool GRID, int S>
+__global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
 {
-    constexpr int LT = 256, T = 16, S = 4;
+    static_assert(S == 2 || S == 4, "samples per thread");
+    constexpr int LT = 256, T = 16;
     __shared__ float4 s_lens[2][LT];
-    const uint32_t tile = blockIdx.x / (uint32_t)f.parts, part = blockIdx.x % (uint32_t)f.parts;
+    const uint32_t tile = blockIdx.x / (uint32_t)parts, part = blockIdx.x % (uint32_t)parts;
     double lo[2], hi[2], c[2], hw[2];
     int64_t i0[2];
     int n[2];
@@ -266,7 +272,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     float px[S], py[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index(part, k, tid);
+        const int si = sample_index<S>(part, k, tid);
         px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]);
         py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]);
     }
@@ -319,7 +325,7 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f)
     const double a01 = h[4], a02 = h[5], j11 = h[6], j12 = h[7], j22 = h[8];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index(part, k, tid);
+        const int si = sample_index<S>(part, k, tid);
         const double d1 = (double)px[k] - c[0], d2 = (double)py[k] - c[1];
         const double r1 = A1[k] * kRcpBiasComp - (a01 + j11 * d1 + j12 * d2);
         const double r2 = A2[k] * kRcpBiasComp - (a02 + j12 * d1 + j22 * d2);
@@ -843,10 +849,21 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_affine, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (f.grid_samples)
-        hipLaunchKernelGGL(k_ff_samples<true>, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
-    else
-        hipLaunchKernelGGL(k_ff_samples<false>, dim3(nt * (uint32_t)f.parts), dim3(256), 0, s, f);
+    // four samples per thread share the most work; with fewer than 4096 such workgroups, two per
+    // thread double the workgroups and keep every compute unit full (same targets either way)
+    const int parts4 = f.n_samples / 1024;
+    if ((int64_t)nt * parts4 >= 4096) {
+        if (f.grid_samples)
+            hipLaunchKernelGGL((k_ff_samples<true, 4>), dim3(nt * (uint32_t)parts4), dim3(256), 0, s, f, parts4);
+        else
+            hipLaunchKernelGGL((k_ff_samples<false, 4>), dim3(nt * (uint32_t)parts4), dim3(256), 0, s, f, parts4);
+    } else {
+        const int parts2 = 2 * parts4;
+        if (f.grid_samples)
+            hipLaunchKernelGGL((k_ff_samples<true, 2>), dim3(nt * (uint32_t)parts2), dim3(256), 0, s, f, parts2);
+        else
+            hipLaunchKernelGGL((k_ff_samples<false, 2>), dim3(nt * (uint32_t)parts2), dim3(256), 0, s, f, parts2);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -457,7 +457,6 @@ rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
     f.samples = c->samples;
     f.init_params = c->init_params;
     f.n_samples = c->n_samples;
-    f.parts = c->n_samples / 1024;
     f.steps = c->steps;
     f.batch = c->batch;
     f.lr = c->lr;

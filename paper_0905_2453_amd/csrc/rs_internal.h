@@ -113,7 +113,7 @@ struct FarArgs {
     const float *init_params;     // kNParams
     float *targets;               // n_tiles x n_samples x 2 (workspace)
     float *state;                 // n_tiles x 3 x kNParams (workspace: master, m, v)
-    int32_t n_samples, parts, steps, batch;
+    int32_t n_samples, steps, batch;
     int32_t grid_samples;         // samples 64 (4 g + k) + i, k = 0..3, share their first coordinate
     float lr;
     float *debug_grad;            // optional n_tiles x kNParams: gradient of the first step

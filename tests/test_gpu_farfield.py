@@ -181,6 +181,35 @@ def test_surrogate_map_error_vs_plain_judge():
     assert l1_aff > 1e-2 and l1_aff > 3 * l1
 
 
+def test_sample_layouts_give_identical_targets():
+    # a fit with many tiles takes four samples per thread, one with few tiles two: the exact
+    # far-field targets of the tiles they share must agree bit for bit
+    torch, P = _env()
+    w = _small_field()
+    dev = torch.device("cuda:0")
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    ut = torch.from_numpy(synth.fit_samples_quads(5, 1024)).to(dev)
+    pt = torch.from_numpy(synth.init_params(5)).to(dev)
+    got = []
+    for tiles in ((64, 64), (4, 2)):          # 4096 tiles (four per thread), 8 tiles (two per thread)
+        win = ((0, 0), (TILE[0] * tiles[0], TILE[1] * tiles[1]))
+        job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi,
+                         w.map_n, counts, lost, window=win)
+        dt = torch.zeros((tiles[0] * tiles[1], 1024, 2), dtype=torch.float32, device=dev)
+        cfg = P.ff_config(ut, pt, tile_rays=TILE, r_near=R_NEAR, steps=1, batch=512, debug_targets=dt,
+                          shared_x=True)
+        model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+        ws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+        P.farfield_fit(job, cfg, model, ws)
+        torch.cuda.synchronize()
+        got.append(dt.cpu().numpy().reshape(tiles[1], tiles[0], 1024, 2))
+        del model, ws
+    assert np.isfinite(got[1]).all() and np.abs(got[1]).max() > 0
+    assert np.array_equal(got[0][:2, :4], got[1])
+
+
 def test_fit_is_deterministic():
     # fixed-order reductions everywhere: two fits of the same input give the same bytes
     torch, P = _env()

@@ -217,7 +217,7 @@ int rs_autotune_batched(const rs_job *jobs, int32_t n_jobs, void *workspace, siz
  * bfloat16, sums in FP32, master weights FP32.
  */
 typedef struct {
-    int32_t tile_rays[2];       /* rays per tile along each axis, e.g. 64 x 64                    */
+    int32_t tile_rays[2];       /* rays per tile along each axis, e.g. 64 x 64; <= 2^24 per tile  */
     double r_near;              /* near radius (Einstein radii), e.g. 8                            */
     int32_t n_samples;          /* fit samples per tile, multiple of 1024, e.g. 4096                */
     int32_t steps;              /* Adam steps (0 = keep the initial parameters), e.g. 2000          */

@@ -15,6 +15,8 @@
 // over hidden units.  So each lane keeps the 32 hidden values of its sample it needs, and the
 // forward pass and the data half of the backward pass need no cross-lane moves.  The weight
 // gradients contract over samples and go through small per-wave LDS transposes.
+#include <algorithm>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -666,13 +668,15 @@ __global__ void k_cells_sort(const CellArgs g)
 
 // ---------------------------------------------------------------- eval: surrogate
 
-// One workgroup per fit tile.  Rays go 128 at a time (32 per wave, a lane pair per ray): far
+// `splits` workgroups per fit tile, workgroup q taking passes q, q + splits, ... of the tile's
+// rays (every ray is computed the same way whatever the split).  Rays go 128 at a time (32 per
+// wave, a lane pair per ray): far
 // field from the affine base plus the network (layers 1-2 on MFMA), near field summed exactly
 // over the candidate lenses of the cells around the tile (far ones masked to zero-mass
 // padding), the two lanes of a ray splitting the lenses; then the FP64 lens equation and
 // wave-aggregated binning into the job's map.
 template <bool DUMP>
-__global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellArgs g)
+__global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellArgs g, int splits)
 {
     constexpr int CAP = 2048, T = 16;
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
@@ -681,7 +685,8 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     __shared__ int s_cells[4];
     __shared__ uint32_t s_lost;
 
-    const uint32_t tile = f.eval_tiles ? (uint32_t)f.eval_tiles[blockIdx.x] : blockIdx.x;
+    const uint32_t item = blockIdx.x / (uint32_t)splits, split = blockIdx.x % (uint32_t)splits;
+    const uint32_t tile = f.eval_tiles ? (uint32_t)f.eval_tiles[item] : item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
     double lo[2], hi[2], c[2], hw[2];
     int64_t i0[2];
@@ -745,7 +750,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
 
     const int n_rays = n[0] * n[1];
     const int passes = (f.TX * f.TY + 127) / 128;
-    for (int ps = 0; ps < passes; ++ps) {
+    for (int ps = (int)split; ps < passes; ps += splits) {
         const int ri = 128 * ps + 32 * wave + col;
         const int ix = ri % f.TX, iy = ri / f.TX;
         const bool active = ri < f.TX * f.TY && ix < n[0] && iy < n[1];
@@ -889,10 +894,13 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
         hipLaunchKernelGGL(k_ff_affine, dim3(grid), dim3(256), 0, s, f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // large tiles are few: split their rays over up to 8 workgroups so that about 4096 run
+    const int passes = (f.TX * f.TY + 127) / 128;
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>({8, passes, (4096 + grid - 1) / grid}));
     if (f.ray_y)
-        hipLaunchKernelGGL((k_surrogate<true>), dim3(grid), dim3(256), 0, s, f, g);
+        hipLaunchKernelGGL((k_surrogate<true>), dim3(grid * (uint32_t)splits), dim3(256), 0, s, f, g, splits);
     else
-        hipLaunchKernelGGL((k_surrogate<false>), dim3(grid), dim3(256), 0, s, f, g);
+        hipLaunchKernelGGL((k_surrogate<false>), dim3(grid * (uint32_t)splits), dim3(256), 0, s, f, g, splits);
     return hipGetLastError();
 }
 

@@ -398,6 +398,8 @@ int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g, bool eval 
     if (job->velocities && !eval)
         return fail(RS_EINVAL, "the far-field fit takes a static field (velocities apply to rs_farfield_eval)");
     if (c->tile_rays[0] <= 0 || c->tile_rays[1] <= 0) return fail(RS_EINVAL, "tile_rays must be > 0");
+    if ((int64_t)c->tile_rays[0] * c->tile_rays[1] > (int64_t(1) << 24))
+        return fail(RS_ERANGE, "tile_rays: at most 2^24 rays per tile");
     if (!(c->r_near > 0.0) || !std::isfinite(c->r_near)) return fail(RS_EINVAL, "r_near must be finite and > 0");
     if (c->n_samples <= 0 || c->n_samples % 1024) return fail(RS_EINVAL, "n_samples must be a positive multiple of 1024");
     if (c->steps < 0) return fail(RS_EINVAL, "steps < 0");

@@ -233,6 +233,12 @@ def test_farfield_validation_without_device():
         assert st == -1, bad
     c = _ffcfg(tile_rays=(ctypes.c_int32 * 2)(0, 16))
     assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0
+    huge = _ffcfg(tile_rays=(ctypes.c_int32 * 2)(4097, 4096))       # more than 2^24 rays per tile
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(huge)) == 0
+    st = L.rs_farfield_fit(ctypes.byref(j), ctypes.byref(huge), ctypes.c_void_p(0x9000), 1 << 30,
+                           ctypes.c_void_p(0xa000), 1 << 30, None)
+    assert st == -2
+    assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(_ffcfg(tile_rays=(ctypes.c_int32 * 2)(4096, 4096)))) > 0
     for bad in (2, -1):
         assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(_ffcfg(shared_x=bad))) == 0
     assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(_ffcfg(shared_x=1))) > 0

@@ -179,61 +179,92 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 
 // ---------------------------------------------------------------- fit: affine base
 
-// One workgroup per tile: alpha_far(c) and its Jacobian over the far set, FP64.  At fit time
-// the result goes into the model's tile header.  For a moving field (eval with velocities) the
-// far set is still the one chosen by the fit-time positions, each far lens enters at its
-// position at f.time, and the result goes to f.affine (only the evaluated tiles).
+// alpha_far(c) and its Jacobian over the far set of each tile, FP64; a workgroup takes
+// kAffTiles consecutive tiles (of the tile list when one is given), so every lens record it
+// loads serves all of them.  Each tile's sums are those of a workgroup of its own: thread t
+// takes lenses t, t + 256, ... in order, then a fixed tree adds the 256 partial sums.  At fit
+// time the result goes into the model's tile header.  For a moving field (eval with
+// velocities) the far set is still the one chosen by the fit-time positions, each far lens
+// enters at its position at f.time, and the result goes to f.affine (only the evaluated tiles).
+constexpr int kAffTiles = 4;
+
 __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 {
     __shared__ double red[4][256];
-    const uint32_t tile = (f.affine && f.eval_tiles) ? (uint32_t)f.eval_tiles[blockIdx.x] : blockIdx.x;
-    double lo[2], hi[2], c[2], hw[2];
-    int64_t i0[2];
-    int n[2];
-    tile_geom(f, tile, lo, hi, c, hw, i0, n);
+    const bool listed = f.affine && f.eval_tiles;
+    const int64_t count = listed ? f.n_eval : f.n_tiles;
+    const int64_t first = (int64_t)blockIdx.x * kAffTiles;
+    const int nt = (int)min((int64_t)kAffTiles, count - first);
+    uint32_t tile[kAffTiles];
+    double lo[kAffTiles][2], hi[kAffTiles][2], c[kAffTiles][2];
+#pragma unroll
+    for (int t = 0; t < kAffTiles; ++t) {
+        // a short last group repeats its last tile; those sums are never written
+        const int64_t e = first + min(t, nt - 1);
+        tile[t] = listed ? (uint32_t)f.eval_tiles[e] : (uint32_t)e;
+        double hw[2];
+        int64_t i0[2];
+        int n[2];
+        tile_geom(f, tile[t], lo[t], hi[t], c[t], hw, i0, n);
+    }
     const double rn2 = f.r_near * f.r_near;
-    double a1 = 0, a2 = 0, j11 = 0, j12 = 0;
+    double a1[kAffTiles], a2[kAffTiles], j11[kAffTiles], j12[kAffTiles];
+#pragma unroll
+    for (int t = 0; t < kAffTiles; ++t) a1[t] = a2[t] = j11[t] = j12[t] = 0.0;
     for (int64_t i = threadIdx.x; i < f.n_lens; i += 256) {
         const float4 l0 = f.lenses[i];
-        if (is_near(l0.x, l0.y, lo, hi, rn2)) continue;
         const float4 l = moved_lens(l0, f.vel, i, f.time);
-        const double dx = c[0] - (double)l.x, dy = c[1] - (double)l.y, m = l.z;
-        const double r2 = dx * dx + dy * dy;
-        const double q = m / r2, q2 = q / r2;
-        a1 += q * dx;
-        a2 += q * dy;
-        j11 += q2 * (dy * dy - dx * dx);
-        j12 += -2.0 * q2 * dx * dy;
+#pragma unroll
+        for (int t = 0; t < kAffTiles; ++t) {
+            if (is_near(l0.x, l0.y, lo[t], hi[t], rn2)) continue;
+            const double dx = c[t][0] - (double)l.x, dy = c[t][1] - (double)l.y, m = l.z;
+            const double r2 = dx * dx + dy * dy;
+            // 1 / r2: the hardware reciprocal refined by two Newton steps (to about 1 ulp), in
+            // place of two IEEE divisions
+            double inv = __builtin_amdgcn_rcp(r2);
+            inv = fma(inv, fma(-r2, inv, 1.0), inv);
+            inv = fma(inv, fma(-r2, inv, 1.0), inv);
+            const double q = m * inv, q2 = q * inv;
+            a1[t] += q * dx;
+            a2[t] += q * dy;
+            j11[t] += q2 * (dy * dy - dx * dx);
+            j12[t] += -2.0 * q2 * dx * dy;
+        }
     }
-    red[0][threadIdx.x] = a1;
-    red[1][threadIdx.x] = a2;
-    red[2][threadIdx.x] = j11;
-    red[3][threadIdx.x] = j12;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+#pragma unroll
+    for (int t = 0; t < kAffTiles; ++t) {
+        if (t >= nt) break;
+        red[0][threadIdx.x] = a1[t];
+        red[1][threadIdx.x] = a2[t];
+        red[2][threadIdx.x] = j11[t];
+        red[3][threadIdx.x] = j12[t];
         __syncthreads();
-    }
-    if (threadIdx.x == 0 && f.affine) {
-        double *o = f.affine + 8 * (size_t)tile;
-        o[0] = red[0][0];
-        o[1] = red[1][0];
-        o[2] = red[2][0];
-        o[3] = red[3][0];
-        o[4] = -red[2][0];
-    } else if (threadIdx.x == 0) {
-        double *h = tile_hdr(f, tile);
-        h[0] = c[0];
-        h[1] = c[1];
-        h[2] = hw[0];
-        h[3] = hw[1];
-        h[4] = red[0][0];
-        h[5] = red[1][0];
-        h[6] = red[2][0];
-        h[7] = red[3][0];
-        h[8] = -red[2][0];
-        h[9] = 1.0;
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && f.affine) {
+            double *o = f.affine + 8 * (size_t)tile[t];
+            o[0] = red[0][0];
+            o[1] = red[1][0];
+            o[2] = red[2][0];
+            o[3] = red[3][0];
+            o[4] = -red[2][0];
+        } else if (threadIdx.x == 0) {
+            double *h = tile_hdr(f, tile[t]);
+            h[0] = c[t][0];
+            h[1] = c[t][1];
+            h[2] = 0.5 * (hi[t][0] - lo[t][0]);
+            h[3] = 0.5 * (hi[t][1] - lo[t][1]);
+            h[4] = red[0][0];
+            h[5] = red[1][0];
+            h[6] = red[2][0];
+            h[7] = red[3][0];
+            h[8] = -red[2][0];
+            h[9] = 1.0;
+        }
+        __syncthreads();   // red[] is reused by the next tile
     }
 }
 
@@ -852,7 +883,7 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
                        f.TX, f.TY);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ff_affine, dim3(nt), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_ff_affine, dim3((nt + kAffTiles - 1) / kAffTiles), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // four samples per thread share the most work; with fewer than 4096 such workgroups, two per
     // thread double the workgroups and keep every compute unit full (same targets either way)
@@ -891,7 +922,7 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
     const uint32_t grid = (uint32_t)(f.eval_tiles ? f.n_eval : f.n_tiles);
     if (grid == 0) return hipSuccess;
     if (f.affine) {
-        hipLaunchKernelGGL(k_ff_affine, dim3(grid), dim3(256), 0, s, f);
+        hipLaunchKernelGGL(k_ff_affine, dim3((grid + kAffTiles - 1) / kAffTiles), dim3(256), 0, s, f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // large tiles are few: split their rays over up to 8 workgroups so that about 4096 run

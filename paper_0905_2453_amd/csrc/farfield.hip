@@ -208,15 +208,27 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
         tile_geom(f, tile[t], lo[t], hi[t], c[t], hw, i0, n);
     }
     const double rn2 = f.r_near * f.r_near;
+    // the group's bounding box: a lens at least r_near from it is at least r_near from each of
+    // its tiles, and the FP64 test is monotone in the box, so skipping the per-tile tests for
+    // such a lens decides exactly as they would
+    double ulo[2] = {lo[0][0], lo[0][1]}, uhi[2] = {hi[0][0], hi[0][1]};
+#pragma unroll
+    for (int t = 1; t < kAffTiles; ++t) {
+        ulo[0] = fmin(ulo[0], lo[t][0]);
+        ulo[1] = fmin(ulo[1], lo[t][1]);
+        uhi[0] = fmax(uhi[0], hi[t][0]);
+        uhi[1] = fmax(uhi[1], hi[t][1]);
+    }
     double a1[kAffTiles], a2[kAffTiles], j11[kAffTiles], j12[kAffTiles];
 #pragma unroll
     for (int t = 0; t < kAffTiles; ++t) a1[t] = a2[t] = j11[t] = j12[t] = 0.0;
     for (int64_t i = threadIdx.x; i < f.n_lens; i += 256) {
         const float4 l0 = f.lenses[i];
         const float4 l = moved_lens(l0, f.vel, i, f.time);
+        const bool near_group = is_near(l0.x, l0.y, ulo, uhi, rn2);
 #pragma unroll
         for (int t = 0; t < kAffTiles; ++t) {
-            if (is_near(l0.x, l0.y, lo[t], hi[t], rn2)) continue;
+            if (near_group && is_near(l0.x, l0.y, lo[t], hi[t], rn2)) continue;
             const double dx = c[t][0] - (double)l.x, dy = c[t][1] - (double)l.y, m = l.z;
             const double r2 = dx * dx + dy * dy;
             // 1 / r2: the hardware reciprocal refined by two Newton steps (to about 1 ulp), in

@@ -179,17 +179,17 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 
 // ---------------------------------------------------------------- fit: affine base
 
-// alpha_far(c) and its Jacobian over the far set of each tile, FP64; a workgroup takes
-// kAffTiles consecutive tiles (of the tile list when one is given), so every lens record it
-// loads serves all of them.  Each tile's sums are those of a workgroup of its own: thread t
+// alpha_far(c) and its Jacobian over the far set of each tile, FP64; a workgroup takes NT
+// consecutive tiles (of the tile list when one is given), so every lens record it loads serves
+// all of them (NT = 4 when there are enough tiles to fill the GPU, else 1).  Each tile's sums are those of a workgroup of its own: thread t
 // takes lenses t, t + 256, ... in order, then a fixed tree adds the 256 partial sums.  At fit
 // time the result goes into the model's tile header.  For a moving field (eval with
 // velocities) the far set is still the one chosen by the fit-time positions, each far lens
 // enters at its position at f.time, and the result goes to f.affine (only the evaluated tiles).
-constexpr int kAffTiles = 4;
-
+template <int NT>
 __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 {
+    constexpr int kAffTiles = NT;
     __shared__ double red[4][256];
     const bool listed = f.affine && f.eval_tiles;
     const int64_t count = listed ? f.n_eval : f.n_tiles;
@@ -888,6 +888,17 @@ __global__ void k_write_model_header(uint8_t *model, uint64_t hash, int64_t n_ti
 
 }  // namespace
 
+// affine bases of `count` tiles: four per workgroup once there are at least 8192 (2048
+// workgroups), else one per workgroup (the sums are the same either way)
+hipError_t launch_affine(const FarArgs &f, int64_t count, hipStream_t s)
+{
+    if (count >= 8192)
+        hipLaunchKernelGGL(k_ff_affine<4>, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, f);
+    else
+        hipLaunchKernelGGL(k_ff_affine<1>, dim3((unsigned)count), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
 hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
 {
     const uint32_t nt = (uint32_t)f.n_tiles;
@@ -895,8 +906,7 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
                        f.TX, f.TY);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ff_affine, dim3((nt + kAffTiles - 1) / kAffTiles), dim3(256), 0, s, f);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_affine(f, nt, s)) != hipSuccess) return e;
     // four samples per thread share the most work; with fewer than 4096 such workgroups, two per
     // thread double the workgroups and keep every compute unit full (same targets either way)
     const int parts4 = f.n_samples / 1024;
@@ -934,8 +944,7 @@ hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s)
     const uint32_t grid = (uint32_t)(f.eval_tiles ? f.n_eval : f.n_tiles);
     if (grid == 0) return hipSuccess;
     if (f.affine) {
-        hipLaunchKernelGGL(k_ff_affine, dim3((grid + kAffTiles - 1) / kAffTiles), dim3(256), 0, s, f);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_affine(f, grid, s)) != hipSuccess) return e;
     }
     // large tiles are few: split their rays over up to 8 workgroups so that about 4096 run
     const int passes = (f.TX * f.TY + 127) / 128;

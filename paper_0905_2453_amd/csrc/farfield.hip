@@ -411,8 +411,8 @@ __global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
 // One workgroup (4 waves) trains one tile's network with mini-batch Adam.  Each wave takes
 // 32-sample chunks; per chunk: forward, output delta, backward through layers 2 and 1, then the
 // weight gradients contract over the chunk's samples through LDS.  The four waves' gradients
-// are summed in a fixed order, then every thread updates its share of the parameters (master
-// weights and Adam moments in global memory, bfloat16 copies in LDS).
+// are summed in a fixed order, then every thread updates its share of the parameters (FP32
+// master weights in global memory; Adam moments and the bfloat16 copies in LDS).
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -426,6 +426,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
     __shared__ float sbias[130];
     __shared__ float red[kNParams];
+    __shared__ float adam_m[kNParams], adam_v[kNParams];   // Adam moments (the master weights stay in global memory)
     // per wave: [unit][sample] staging of dz2, h1, dz1 and h2 (4 x 64 x 32 bfloat16 each); after
     // a step's last round the same 64 KB hold waves 1-3's gradients for the reduction
     __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * 4 * 64 * 32];
@@ -435,14 +436,14 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
 
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
-    float *state = f.state + (size_t)tile * 3 * kNParams;  // master, m, v
+    float *state = f.state + (size_t)tile * kNParams;  // FP32 master weights
     const float *tgt = f.targets + (size_t)tile * f.n_samples * 2;
 
     for (int p = tid; p < kNParams; p += 256) {
         const float w = f.init_params[p];
         state[p] = w;
-        state[kNParams + p] = 0.f;
-        state[2 * kNParams + p] = 0.f;
+        adam_m[p] = 0.f;
+        adam_v[p] = 0.f;
         const uint16_t b = to_bf16(w);
         Wbf[p] = b;
         if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
@@ -604,8 +605,8 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                 const int p = tid + 256 * (k0 + kk);
                 if (p < kNParams) {
                     sw[kk] = state[p];
-                    sm[kk] = state[kNParams + p];
-                    sv[kk] = state[2 * kNParams + p];
+                    sm[kk] = adam_m[p];
+                    sv[kk] = adam_v[p];
                 }
             }
 #pragma unroll
@@ -619,8 +620,8 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                 v = 0.999f * v + 0.001f * g * g;
                 w -= lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
                 state[p] = w;
-                state[kNParams + p] = m;
-                state[2 * kNParams + p] = v;
+                adam_m[p] = m;
+                adam_v[p] = v;
                 const uint16_t b = to_bf16(w);
                 Wbf[p] = b;
                 if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;

@@ -484,7 +484,7 @@ rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
 size_t fit_ws_bytes(const FarGeom &g, const rs_ff_config *c)
 {
     return align256((size_t)g.n_tiles * c->n_samples * 2 * sizeof(float)) +
-           align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)) + 256;
+           align256((size_t)g.n_tiles * rs::kNParams * sizeof(float)) + 256;
 }
 
 // Cell grid around the ray window grown by r_near (plus one cell): only lenses there can be near.

@@ -87,6 +87,21 @@ def test_zoom_equals_fine_grid_paper_field(block, jitter):
     assert st["cells_kept"] < 0.06 * st["cells"] and st["slots_shot"] < 0.06 * st["slots"]
 
 
+@pytest.mark.parametrize("block,jitter,cell", [((2, 4), None, (5, 7)), ((1, 4), 29, (0, 0)), ((4, 2), 3, (3, 9))])
+def test_zoom_odd_window_blocks_and_jitter(block, jitter, cell):
+    # a window starting on an odd row and column, several lane shapes, jittered rays and odd cell
+    # sizes: the zoom still adds exactly the plain shoot's counts (row pairs stay aligned)
+    torch, P = _env()
+    w = synth.workload_paper(n_lens=20000, grid=4096)
+    o = P.Opts()
+    o.block_cols, o.block_rows = block
+    win = ((1001, 777), (1999, 2501))
+    cp, cz, st = _run(w, w.grid_n, (0.5, -3.0), (3.0, -0.5), (200, 200), window=win, opts=o,
+                      jitter_seed=jitter, zoom=P.zoom_params(cell))
+    assert cp.sum() > 0 and np.array_equal(cp, cz), (block, jitter, cell)
+    assert st["slots_shot"] < st["slots"]
+
+
 def test_zoom_window_cells_and_margin():
     # a ray window that is not a multiple of the tile or cell sizes, explicit cells and a margin
     torch, P = _env()

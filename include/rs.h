@@ -30,7 +30,9 @@
  * Ownership and memory
  *   - Every pointer marked "device" is device memory owned by the caller.
  *     The library never allocates device memory: workspace sizes come from
- *     the *_bytes queries and the caller passes the buffers in.
+ *     the *_bytes queries and the caller passes the buffers in.  The one
+ *     exception is rs_shoot_noalloc's fixed scratch array, a device global of
+ *     the library's code object (see there).
  *   - Host structs are read during the call only.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
  *     enqueued asynchronously; kernel faults surface on the caller's next
@@ -165,6 +167,20 @@ size_t rs_workspace_bytes(const rs_job *job, const rs_opts *opts);
  * arguments, RS_EDEVICE if a launch fails.  An empty window is a no-op.
  */
 int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, const rs_opts *opts);
+
+/*
+ * rs_shoot without a workspace, for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.  It computes
+ * exactly what rs_shoot computes (same kernels, same counts and dumps), but its 8 partial maps
+ * live in a fixed device array inside the library (32 MiB, held by every GPU the library runs
+ * on until the process ends) instead of a caller workspace.  The map may have at most 2^20
+ * bins (1024 x 1024); larger maps return RS_ERANGE before any HIP call (use rs_shoot).  The
+ * first call on a device looks up the array's address there (hipGetSymbolAddress); no call
+ * allocates or frees anything.  All calls on one GPU share that GPU's array and every call
+ * clears the part it uses, so calls that overlap on one GPU (e.g. on two streams) race: order
+ * them on one stream.  Errors as for rs_shoot.
+ */
+int rs_shoot_noalloc(const rs_job *job, void *stream, const rs_opts *opts);
 
 /*
  * Many maps in one persistent launch (many independent map generations, section 4; each map is

@@ -148,6 +148,12 @@ def shoot_job(job: _abi.Job, workspace, opts: Opts | None = None, stream=None) -
                           _stream_handle(stream), ctypes.byref(opts) if opts else None))
 
 
+def shoot_job_noalloc(job: _abi.Job, opts: Opts | None = None, stream=None) -> None:
+    """rs_shoot_noalloc: rs_shoot with the library's fixed scratch instead of a workspace (maps of at
+    most 1024 x 1024 bins; calls on one GPU must not overlap)."""
+    _check(lib().rs_shoot_noalloc(ctypes.byref(job), _stream_handle(stream), ctypes.byref(opts) if opts else None))
+
+
 def zoom_params(cell=(0, 0), margin=0.0) -> _abi.Zoom:
     z = _abi.Zoom()
     z.cell[0], z.cell[1] = int(cell[0]), int(cell[1])

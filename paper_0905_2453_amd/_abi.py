@@ -80,6 +80,7 @@ EXPORTS = [
     ("rs_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.POINTER(Opts)]),
     ("rs_shoot", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                 ctypes.POINTER(Opts)]),
+    ("rs_shoot_noalloc", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.POINTER(Opts)]),
     ("rs_batched_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.c_int32]),
     ("rs_shoot_batched", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.POINTER(Opts)]),

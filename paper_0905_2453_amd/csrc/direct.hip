@@ -14,6 +14,7 @@
 // reads the same record, so each LDS read is a broadcast.  Partial sums run in float32 over
 // T consecutive lenses, then are added to a per-ray FP64 accumulator.
 #include <algorithm>
+#include <mutex>
 
 #include "rs_internal.h"
 
@@ -711,6 +712,35 @@ hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride,
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(256), 0, s, partial, bins, pstride, counts);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- allocation-free shooting
+
+// The partial maps of rs_shoot_noalloc: kPartials maps of at most kNoAllocBins bins, in a fixed
+// device array that every GPU the library runs on holds (its own copy) until the process ends.
+// On the host this name is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, resolved once per device below.
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+hipError_t noalloc_scratch(uint32_t **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = static_cast<uint32_t *>(addr[dev]);
+    return hipSuccess;
 }
 
 }  // namespace rs

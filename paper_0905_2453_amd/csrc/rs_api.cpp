@@ -501,6 +501,22 @@ void cell_geom(const rs_job *job, const rs_ff_config *c, const FarGeom &g, doubl
     ncy = (int64_t)std::ceil((y1 + c->r_near + g.cs - oy) / g.cs);
 }
 
+// The three launches of one plain map: clear the kPartials partial maps at `part` (a fill kernel,
+// never hipMemsetAsync), run the direct sum into them, add them into the caller's map.
+int shoot_with_partials(const rs_job *job, const Tune &t, uint32_t *part, hipStream_t s, const rs_opts *opts)
+{
+    const int64_t pstride = partial_stride(job);
+    const int64_t bins = (int64_t)job->map.n[0] * job->map.n[1];
+    const rs::DirectArgs a = make_args(job, t, part, pstride, opts);
+    hipError_t e = rs::launch_zero(part, rs::kPartials * pstride, s);
+    if (e != hipSuccess) return dev_fail(e, "zero partial maps");
+    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, tile_count(job, t), s);
+    if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
+    e = rs::launch_reduce(part, bins, pstride, job->counts, s);
+    if (e != hipSuccess) return dev_fail(e, "map reduce launch");
+    return RS_OK;
+}
+
 size_t eval_ws_bytes(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
 {
     double ox, oy;
@@ -554,22 +570,29 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
 
     const rs_raygrid &g = job->grid;
     if (g.win_n[0] == 0 || g.win_n[1] == 0) return RS_OK;
-
+    if (tile_count(job, t) >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
     uint32_t *part = reinterpret_cast<uint32_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    const int64_t pstride = partial_stride(job);
-    const int64_t bins = (int64_t)job->map.n[0] * job->map.n[1];
-    const rs::DirectArgs a = make_args(job, t, part, pstride, opts);
-    const int64_t n_tiles = tile_count(job, t);
-    if (n_tiles >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
+    return shoot_with_partials(job, t, part, reinterpret_cast<hipStream_t>(stream), opts);
+}
 
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = rs::launch_zero(part, rs::kPartials * pstride, s);
-    if (e != hipSuccess) return dev_fail(e, "zero partial maps");
-    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, n_tiles, s);
-    if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
-    e = rs::launch_reduce(part, bins, pstride, job->counts, s);
-    if (e != hipSuccess) return dev_fail(e, "map reduce launch");
-    return RS_OK;
+int rs_shoot_noalloc(const rs_job *job, void *stream, const rs_opts *opts)
+{
+    g_err[0] = '\0';
+    int st = validate_job(job);
+    if (st != RS_OK) return st;
+    Tune t;
+    if ((st = resolve_opts(opts, t)) != RS_OK) return st;
+    if (partial_stride(job) > rs::kNoAllocBins)
+        return fail(RS_ERANGE, "map of %lld bins: rs_shoot_noalloc takes at most %d (1024 x 1024); use rs_shoot",
+                    (long long)((int64_t)job->map.n[0] * job->map.n[1]), rs::kNoAllocBins);
+    if (opts && (opts->flags & RS_FLAG_FAULT_INJECT)) return fail(RS_EDEVICE, "injected fault (RS_FLAG_FAULT_INJECT)");
+    const rs_raygrid &g = job->grid;
+    if (g.win_n[0] == 0 || g.win_n[1] == 0) return RS_OK;
+    if (tile_count(job, t) >= (int64_t(1) << 31)) return fail(RS_ERANGE, "too many ray tiles");
+    uint32_t *part = nullptr;   // the library's fixed scratch array on the current device
+    const hipError_t e = rs::noalloc_scratch(&part);
+    if (e != hipSuccess) return dev_fail(e, "scratch address (hipGetSymbolAddress)");
+    return shoot_with_partials(job, t, part, reinterpret_cast<hipStream_t>(stream), opts);
 }
 
 // ---------------------------------------------------------------- zoom

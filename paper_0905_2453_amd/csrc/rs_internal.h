@@ -14,6 +14,8 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxWindow = 64;          // LDS map window side (bins)
 constexpr int kPartials = 8;            // partial maps, one per accelerator complex die
 constexpr float kPadCoord = 1.0e18f;    // position of the zero-mass lenses padding a tile
+constexpr int kNoAllocBins = 1 << 20;   // largest map rs_shoot_noalloc takes (1024 x 1024 bins)
+constexpr int64_t kNoAllocWords = (int64_t)kPartials * kNoAllocBins;   // its fixed scratch: 32 MiB
 
 // Everything one direct-sum launch needs, already reduced to FP64 constants on the host.
 struct DirectArgs {
@@ -223,5 +225,8 @@ hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s);
 // counts[b] += sum_s partial[s * pstride + b] for b < bins.
 hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride, uint32_t *counts,
                          hipStream_t s);
+// Device address of the fixed scratch array (kNoAllocWords words) on the current device, looked up
+// with hipGetSymbolAddress on the first call per device.
+hipError_t noalloc_scratch(uint32_t **ptr);
 
 }  // namespace rs

@@ -177,6 +177,29 @@ def test_fault_injection_reports_device_error_without_launch():
     assert ei.value.status == -3
 
 
+def test_noalloc_validation_without_device():
+    # rs_shoot_noalloc checks its arguments and the size of its fixed scratch before any HIP call
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+
+    def call(job, opts=None):
+        return L.rs_shoot_noalloc(ctypes.byref(job), None, ctypes.byref(opts) if opts is not None else None)
+
+    assert call(_job(n_lens=-1)) == -1
+    big = _job()
+    big.map.n[0], big.map.n[1] = 1025, 1024
+    assert call(big) == -2 and b"at most" in L.rs_last_error()
+    edge = _job(**{"grid.win_n": (0, 0)})
+    edge.map.n[0], edge.map.n[1] = 1024, 1024
+    assert call(edge) == 0                     # the largest map, empty window: nothing to launch
+    o = _abi.Opts()
+    o.flags = _abi.RS_FLAG_FAULT_INJECT
+    assert call(_job(), o) == -3 and b"injected" in L.rs_last_error()
+    o = _abi.Opts()
+    o.block_cols, o.block_rows = 3, 3
+    assert call(_job(), o) == -1
+
+
 def test_version_string():
     P, L = _lib()
     assert b"gfx950" in L.rs_version()

@@ -118,7 +118,7 @@ typedef struct {
     rs_map map;
     uint32_t *counts;        /* device, map.n[1] * map.n[0], ACCUMULATED (+=)                */
     uint64_t *n_lost;        /* device, one counter, ACCUMULATED (+=)                        */
-    /* Moving lenses (section 5: stars move between frames).  velocities: device, n_lens x
+    /* Moving lenses (section 4: stars move between frames).  velocities: device, n_lens x
      * (v1, v2) float32, or NULL for a static field.  The job then shoots the field at `time`:
      * lens i sits at float32((double)x_i + (double)v_i * time) per axis (FP64, then rounded),
      * its mass unchanged.  rs_shoot, rs_shoot_batched and rs_shoot_zoom apply it while staging
@@ -181,6 +181,24 @@ int rs_shoot(const rs_job *job, void *workspace, size_t ws_bytes, void *stream, 
  * them on one stream.  Errors as for rs_shoot.
  */
 int rs_shoot_noalloc(const rs_job *job, void *stream, const rs_opts *opts);
+
+/*
+ * Magnification map (section 1, eq. 4): mu_ij = N_ij / N_av, where N_av, the number of rays a
+ * pixel receives without lensing, is the pixel area over the ray-cell area,
+ *     N_av = (dy1 dy2) / (dx1 dx2),  dy_k = (map hi_k - lo_k) / n_k,  dx_k = (grid hi_k - lo_k) / n_k,
+ * evaluated in FP64 in that order (one ray per grid cell, centred or jittered alike; the grid's
+ * window is ignored).
+ *   counts: device, map->n[1] x map->n[0] uint32 (the layout rs_shoot fills)
+ *   mu:     device output, the same number of doubles, mu[b] = (double)counts[b] / N_av (IEEE
+ *           division); counts and mu must not overlap
+ *   n_av_out: host, nullable; receives N_av (also when counts or mu is NULL, which then returns
+ *           RS_EINVAL after filling it)
+ * A map accumulated over k passes of the same grid holds k times the counts: divide mu by k.
+ * Errors: RS_EINVAL for a bad grid or map or a NULL buffer, RS_ERANGE for >= 2^31 pixels or a
+ * non-finite N_av, RS_EDEVICE if the launch fails.  Asynchronous on `stream`.
+ */
+int rs_magnification(const uint32_t *counts, const rs_raygrid *grid, const rs_map *map, double *mu,
+                     double *n_av_out, void *stream);
 
 /*
  * Many maps in one persistent launch (many independent map generations, section 4; each map is
@@ -258,7 +276,8 @@ typedef struct {
  * n_tiles bytes: 10 doubles (c1, c2, h1, h2, alpha_far(c) 1, 2, J11, J12, J22, s_t) padded to
  * 128 bytes, the 5378 parameters as bfloat16 (W1 [64][16], b1, W2 [64][64], b2, W3 [2][64], b3)
  * padded to 16 bytes, then b1, b2, b3 again as 130 floats.  The hash covers the ray grid,
- * window, tiling, fit settings and lens count (not the lens positions).
+ * window, tiling, fit settings and lens count; the header also keeps a 64-bit checksum of the
+ * lens records the fit saw, which rs_farfield_eval recomputes (one pass over the lens array).
  */
 size_t rs_farfield_model_bytes(const rs_job *job, const rs_ff_config *cfg);
 size_t rs_farfield_fit_workspace_bytes(const rs_job *job, const rs_ff_config *cfg);
@@ -277,8 +296,9 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
  * RS_FLAG_AFFINE_ONLY (network off: the method without the learned part).  With
  * cfg->eval_tiles only the listed tiles are shot (e.g. a seeded subset judged against
  * rs_shoot on the same tile windows).  Reads the model header and the tile list first
- * (synchronises the stream); RS_ENOTFIT on a model mismatch, RS_EINVAL on a bad tile index.
- * Moving field (section 5, one closure reused across frames): with job->velocities the job's
+ * (synchronises the stream); RS_ENOTFIT on a model mismatch (grid, tiling, configuration or
+ * lens records other than the fit's), RS_EINVAL on a bad tile index.
+ * Moving field (section 4, one closure reused across frames): with job->velocities the job's
  * lens positions are those of the fit; each tile's near set is still chosen by them, its
  * lenses enter at their positions at job->time; the far set's affine base alpha_far(c),
  * J_far(c) is recomputed in FP64 at job->time, and the fitted network residual is kept.
@@ -306,7 +326,7 @@ int rs_plan_grid(const rs_map *map, const rs_macro *macro, double kappa_star, do
                  double margin, rs_raygrid *out, double *n_av_out);
 
 /*
- * Moving lenses (section 5): out[i] = (float32(x1_i + v1_i t), float32(x2_i + v2_i t), m_i, pad_i),
+ * Moving lenses (section 4): out[i] = (float32(x1_i + v1_i t), float32(x2_i + v2_i t), m_i, pad_i),
  * the same positions a job with `velocities` and `time` shoots.  lenses, velocities (n x 2
  * float32) and out (n records) are device memory; out may equal lenses.  Asynchronous.
  */
@@ -314,7 +334,7 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
                       void *stream);
 
 /*
- * Interactive zoom (section 5: a selected area of a map recomputed at higher detail).
+ * Interactive zoom (section 4: a selected area of a map recomputed at higher detail).
  * `job` describes the dense problem: job->grid is the fine ray grid (and window) and job->map the
  * selected source-plane area at the wanted resolution.  The counts added to job->counts are
  * exactly those rs_shoot(job) would add, bit for bit, but only the rays that can reach the map
@@ -322,9 +342,10 @@ int rs_advance_lenses(const rs_lens *lenses, const float *velocities, int64_t n,
  * under eq. 6 is bounded from its centre (deflection, its gradient, a second-order remainder
  * over the lenses beyond three half-diagonals, 2 m / distance for closer lenses; a cell that
  * holds a lens is always kept), widened by a float32 rounding allowance and zoom->margin.  The
- * bounds are taken coarse to fine over three levels (cells grouped 4 x 4, then 16 x 16), a
- * level looking only inside the cells kept above it; the rays of the finest cells kept are
- * shot with the plain path's arithmetic.
+ * bounds are taken coarse to fine over five levels: the coarsest groups 16 x 16 culling cells,
+ * each later level halves the cell side (its cells are the 2 x 2 children of the cells kept at
+ * the level above, and it looks only inside those), the last is the culling cells themselves;
+ * the rays of the finest cells kept are shot with the plain path's arithmetic.
  * *job->n_lost receives only the shot rays that miss the map.  opts as for rs_shoot, except
  * that per-ray dumps are rejected (RS_EINVAL).
  */
@@ -372,7 +393,7 @@ typedef struct {
  * tracks: device, n_tracks x 4 doubles (start1, start2, end1, end2), finite.
  * mu, mag: device outputs of n_tracks x n_points doubles, track-major (either may be NULL).
  * frame_stride: 0 reads one map for every point; otherwise point k of every track reads the
- * map at counts + k frame_stride (a time-evolving field, section 5: one frame per point, e.g.
+ * map at counts + k frame_stride (a time-evolving field, section 4: one frame per point, e.g.
  * the maps of a batch of moving-lens jobs); frame_stride >= map->n[0] map->n[1].
  * Nothing is allocated; asynchronous on `stream`.  n_tracks = 0 is a no-op.
  * Errors: RS_EINVAL for a bad map, n_av <= 0, source, sizes or stride; RS_EDEVICE if the launch

@@ -165,7 +165,7 @@ def shoot_parallel(w, window=None, threads: int = 8) -> tuple[np.ndarray, int]:
 
 
 def lenses_at(lenses, velocities, t: float) -> np.ndarray:
-    """Lens records of a moving field at time t (section 5: stars move between frames).
+    """Lens records of a moving field at time t (section 4: stars move between frames).
 
     Reading (the paper names the effect, not a motion model): each lens moves on a straight line
     at constant velocity, x_i(t) = x_i + v_i t, evaluated in FP64 from the float32 record and

@@ -39,7 +39,7 @@ def light_curve(counts, map_lo, map_hi, map_n, n_av, tracks, n_points, kind="gau
     the weight sum of every point.
 
     counts is one map read by every point, or a stack of n_points maps of which point k reads
-    map k (a field whose lenses move between the frames, section 5)."""
+    map k (a field whose lenses move between the frames, section 4)."""
     pix = int(map_n[0]) * int(map_n[1])
     counts = np.asarray(counts)
     if counts.size == pix:

@@ -1,6 +1,6 @@
 """FP64 oracle of the zoom's cell bound -- TEST INFRASTRUCTURE ONLY.
 
-A zoom (section 5: a selected source-plane area recomputed at higher ray density) may skip an
+A zoom (section 4: a selected source-plane area recomputed at higher ray density) may skip an
 image-plane cell only if no ray in it can land in the area.  For the rectangle c +- h of the
 image plane and the lens equation y = diag(l1, l2) x - alpha(x) (eqs. 1, 2, 6) this module
 bounds y over the rectangle, written from the mathematics:

@@ -154,6 +154,32 @@ def shoot_job_noalloc(job: _abi.Job, opts: Opts | None = None, stream=None) -> N
     _check(lib().rs_shoot_noalloc(ctypes.byref(job), _stream_handle(stream), ctypes.byref(opts) if opts else None))
 
 
+def magnification(counts, grid_lo, grid_hi, grid_n, map_lo, map_hi, map_n, mu=None, stream=None):
+    """rs_magnification: mu = counts / N_av (FP64, eq. 4) on the device; returns (mu, N_av).
+
+    counts: the int32 view of a map (map_n[1] x map_n[0]); mu: optional float64 tensor of the same
+    shape (allocated when None)."""
+    torch = _torch()
+    _require_cuda(counts, "counts", torch.int32)
+    if counts.numel() != int(map_n[0]) * int(map_n[1]):
+        raise ValueError("counts must hold map_n[1] * map_n[0] bins")
+    if mu is None:
+        mu = torch.empty(counts.shape, dtype=torch.float64, device=counts.device)
+    _require_cuda(mu, "mu", torch.float64)
+    if mu.numel() != counts.numel():
+        raise ValueError("mu must have as many elements as counts")
+    g = _abi.RayGrid()
+    m = _abi.Map()
+    for k in range(2):
+        g.lo[k], g.hi[k], g.n[k] = float(grid_lo[k]), float(grid_hi[k]), int(grid_n[k])
+        g.win_n[k] = int(grid_n[k])
+        m.lo[k], m.hi[k], m.n[k] = float(map_lo[k]), float(map_hi[k]), int(map_n[k])
+    nav = ctypes.c_double()
+    _check(lib().rs_magnification(ctypes.c_void_p(counts.data_ptr()), ctypes.byref(g), ctypes.byref(m),
+                                  ctypes.c_void_p(mu.data_ptr()), ctypes.byref(nav), _stream_handle(stream)))
+    return mu, nav.value
+
+
 def zoom_params(cell=(0, 0), margin=0.0) -> _abi.Zoom:
     z = _abi.Zoom()
     z.cell[0], z.cell[1] = int(cell[0]), int(cell[1])

@@ -81,6 +81,8 @@ EXPORTS = [
     ("rs_shoot", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                 ctypes.POINTER(Opts)]),
     ("rs_shoot_noalloc", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_void_p, ctypes.POINTER(Opts)]),
+    ("rs_magnification", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RayGrid), ctypes.POINTER(Map),
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("rs_batched_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Job), ctypes.c_int32]),
     ("rs_shoot_batched", ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.POINTER(Opts)]),

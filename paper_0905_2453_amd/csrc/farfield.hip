@@ -885,9 +885,35 @@ __global__ void k_write_model_header(uint8_t *model, uint64_t hash, int64_t n_ti
     d[1] = tiles_y;
     d[2] = TX;
     d[3] = TY;
+    h[5] = 0;   // lens checksum, added by k_lens_checksum
+}
+
+// *out += sum over lens records i of mix64(bits of (x1, x2) + (i + 1) G) + mix64(bits of (m, pad) ^ i):
+// a checksum of the lens array that does not depend on the order of the additions (wrapping
+// 64-bit sums), one atomic per wave.
+__global__ void __launch_bounds__(256) k_lens_checksum(const float4 *lenses, int64_t n, unsigned long long *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint4 v = reinterpret_cast<const uint4 *>(lenses)[i];
+        const uint64_t a = ((uint64_t)v.y << 32) | v.x, b = ((uint64_t)v.w << 32) | v.z;
+        acc += mix64(a + (uint64_t)(i + 1) * kGolden) + mix64(b ^ (uint64_t)i);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
 }  // namespace
+
+hipError_t launch_lens_checksum(const float4 *lenses, int64_t n, unsigned long long *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(k_lens_checksum, dim3((unsigned)blocks), dim3(256), 0, s, lenses, n, out);
+    return hipGetLastError();
+}
 
 // affine bases of `count` tiles: four per workgroup once there are at least 8192 (2048
 // workgroups), else one per workgroup (the sums are the same either way)
@@ -907,6 +933,9 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
                        f.TX, f.TY);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_lens_checksum(f.lenses, f.n_lens, reinterpret_cast<unsigned long long *>(f.model + 40), s)) !=
+        hipSuccess)
+        return e;
     if ((e = launch_affine(f, nt, s)) != hipSuccess) return e;
     // four samples per thread share the most work; with fewer than 4096 such workgroups, two per
     // thread double the workgroups and keep every compute unit full (same targets either way)

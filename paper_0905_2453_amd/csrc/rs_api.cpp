@@ -524,7 +524,14 @@ size_t eval_ws_bytes(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
     cell_geom(job, c, g, ox, oy, ncx, ncy);
     const size_t cells = (size_t)(ncx * ncy);
     return align256(cells * 4) * 2 + align256((cells + 1) * 4) + align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4) +
-           align256((size_t)g.n_tiles * 8 * sizeof(double)) + 256;
+           align256((size_t)g.n_tiles * 8 * sizeof(double)) + 256 + 256;
+}
+
+// Offset of the lens checksum word in the eval workspace (after the cell lists and affine bases).
+size_t eval_checksum_off(const rs_job *job, const FarGeom &g, size_t cells)
+{
+    return align256(cells * 4) * 2 + align256((cells + 1) * 4) + align256((size_t)std::max<int64_t>(job->n_lens, 1) * 4) +
+           align256((size_t)g.n_tiles * 8 * sizeof(double));
 }
 
 }  // namespace
@@ -593,6 +600,34 @@ int rs_shoot_noalloc(const rs_job *job, void *stream, const rs_opts *opts)
     const hipError_t e = rs::noalloc_scratch(&part);
     if (e != hipSuccess) return dev_fail(e, "scratch address (hipGetSymbolAddress)");
     return shoot_with_partials(job, t, part, reinterpret_cast<hipStream_t>(stream), opts);
+}
+
+// ---------------------------------------------------------------- magnification (eq. 4)
+
+int rs_magnification(const uint32_t *counts, const rs_raygrid *grid, const rs_map *map, double *mu,
+                     double *n_av_out, void *stream)
+{
+    g_err[0] = '\0';
+    if (!grid || !map) return fail(RS_EINVAL, "grid or map is NULL");
+    for (int k = 0; k < 2; ++k) {
+        if (!is_fin(grid->lo[k]) || !is_fin(grid->hi[k]) || !(grid->hi[k] > grid->lo[k]) || grid->n[k] <= 0)
+            return fail(RS_EINVAL, "grid axis %d: need finite lo < hi and n > 0", k);
+        if (!is_fin(map->lo[k]) || !is_fin(map->hi[k]) || !(map->hi[k] > map->lo[k]) || map->n[k] <= 0)
+            return fail(RS_EINVAL, "map axis %d: need finite lo < hi and n > 0", k);
+    }
+    const int64_t bins = (int64_t)map->n[0] * map->n[1];
+    if (bins >= (int64_t(1) << 31)) return fail(RS_ERANGE, "map has >= 2^31 pixels");
+    // N_av: rays per pixel without lensing = pixel area / ray-cell area
+    const double dx1 = (grid->hi[0] - grid->lo[0]) / (double)grid->n[0];
+    const double dx2 = (grid->hi[1] - grid->lo[1]) / (double)grid->n[1];
+    const double dy1 = (map->hi[0] - map->lo[0]) / (double)map->n[0];
+    const double dy2 = (map->hi[1] - map->lo[1]) / (double)map->n[1];
+    const double n_av = dy1 * dy2 / (dx1 * dx2);
+    if (!is_fin(n_av) || !(n_av > 0.0)) return fail(RS_ERANGE, "N_av is not a finite positive number");
+    if (n_av_out) *n_av_out = n_av;
+    if (!counts || !mu) return fail(RS_EINVAL, "counts or mu is NULL");
+    const hipError_t e = rs::launch_magnification(counts, bins, n_av, mu, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RS_OK : dev_fail(e, "magnification launch");
 }
 
 // ---------------------------------------------------------------- zoom
@@ -856,15 +891,25 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     // the model must have been fitted for this grid, tiling and configuration
     if (cfg->n_eval_tiles < 0 || (cfg->n_eval_tiles > 0 && !cfg->eval_tiles))
         return fail(RS_EINVAL, "eval_tiles / n_eval_tiles inconsistent");
-    uint64_t hdr[2] = {0, 0};
+    // ... and on this lens array: its checksum, computed now, must equal the one the fit stored
+    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    const size_t cells = (size_t)(ncx * ncy);
+    uint64_t *csum = reinterpret_cast<uint64_t *>(base + eval_checksum_off(job, g, cells));
+    uint64_t hdr[6] = {0, 0, 0, 0, 0, 0}, lens_sum = 0;
     std::vector<int32_t> tl(cfg->eval_tiles ? (size_t)cfg->n_eval_tiles : 0);
-    hipError_t e = hipMemcpyAsync(hdr, model, sizeof hdr, hipMemcpyDeviceToHost, s);
+    hipError_t e = rs::launch_fill_u32(reinterpret_cast<uint32_t *>(csum), 2, 0u, s);
+    if (e == hipSuccess)
+        e = rs::launch_lens_checksum(reinterpret_cast<const float4 *>(job->lenses), job->n_lens,
+                                     reinterpret_cast<unsigned long long *>(csum), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hdr, model, sizeof hdr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&lens_sum, csum, sizeof lens_sum, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && !tl.empty())
         e = hipMemcpyAsync(tl.data(), cfg->eval_tiles, tl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return dev_fail(e, "model header read");
     if (hdr[0] != rs::kModelMagic || hdr[1] != ff_hash(job, cfg))
         return fail(RS_ENOTFIT, "model was not fitted for this job and configuration");
+    if (hdr[5] != lens_sum) return fail(RS_ENOTFIT, "model was fitted on a different lens array (checksum differs)");
     {
         std::vector<char> seen((size_t)g.n_tiles, 0);
         for (int32_t t : tl) {
@@ -879,8 +924,6 @@ int rs_farfield_eval(const rs_job *job, const rs_ff_config *cfg, const void *mod
     f.affine_only = (opts && (opts->flags & RS_FLAG_AFFINE_ONLY)) ? 1 : 0;
     f.eval_tiles = cfg->eval_tiles;
     f.n_eval = cfg->eval_tiles ? cfg->n_eval_tiles : g.n_tiles;
-    uint8_t *base = reinterpret_cast<uint8_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    const size_t cells = (size_t)(ncx * ncy);
     rs::CellArgs cg{};
     cg.lenses = f.lenses;
     cg.n_lens = job->n_lens;

@@ -149,6 +149,8 @@ struct CellArgs {
 };
 
 hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s);
+// *out += an order-independent 64-bit checksum of n lens records (the caller zeroes *out).
+hipError_t launch_lens_checksum(const float4 *lenses, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_ff_eval(const FarArgs &f, const CellArgs &g, hipStream_t s);
 
 // ---------------------------------------------------------------- zoom
@@ -225,6 +227,8 @@ hipError_t launch_zero(uint32_t *p, int64_t n_words, hipStream_t s);
 // counts[b] += sum_s partial[s * pstride + b] for b < bins.
 hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride, uint32_t *counts,
                          hipStream_t s);
+// mu[b] = counts[b] / n_av for b < bins (FP64).
+hipError_t launch_magnification(const uint32_t *counts, int64_t bins, double n_av, double *mu, hipStream_t s);
 // Device address of the fixed scratch array (kNoAllocWords words) on the current device, looked up
 // with hipGetSymbolAddress on the first call per device.
 hipError_t noalloc_scratch(uint32_t **ptr);

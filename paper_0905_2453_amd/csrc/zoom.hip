@@ -1,4 +1,4 @@
-// Interactive zoom (section 5: a selected area of a map recomputed at higher ray density).
+// Interactive zoom (section 4: a selected area of a map recomputed at higher ray density).
 //
 // The zoom map is, by definition, the map that shooting EVERY ray of the fine grid would give on
 // the selected source-plane window.  Only rays that can land in the window matter, so the fine

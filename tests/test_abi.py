@@ -200,6 +200,42 @@ def test_noalloc_validation_without_device():
     assert call(_job(), o) == -1
 
 
+def test_magnification_validation_and_n_av_without_device():
+    # rs_magnification computes N_av on the host before any HIP call: with NULL buffers it returns
+    # RS_EINVAL after filling N_av, which must equal the oracle's pixel area / ray-cell area bit for bit
+    import oracle
+    import synth
+    P, L = _lib()
+    from paper_0905_2453_amd import _abi
+
+    def grid_map(w):
+        g, m = _abi.RayGrid(), _abi.Map()
+        for k in range(2):
+            g.lo[k], g.hi[k], g.n[k] = w.grid_lo[k], w.grid_hi[k], w.grid_n[k]
+            m.lo[k], m.hi[k], m.n[k] = w.map_lo[k], w.map_hi[k], w.map_n[k]
+        return g, m
+
+    for w in (synth.workload_small(), synth.workload_paper(n_lens=10), synth.workload_farfield(n_lens=10)):
+        g, m = grid_map(w)
+        nav = ctypes.c_double(-1.0)
+        st = L.rs_magnification(None, ctypes.byref(g), ctypes.byref(m), None, ctypes.byref(nav), None)
+        assert st == -1 and nav.value == oracle.n_av(w), (w.name, nav.value, oracle.n_av(w))
+    g, m = grid_map(synth.workload_small())
+    assert L.rs_magnification(ctypes.c_void_p(0x1000), None, ctypes.byref(m), ctypes.c_void_p(0x2000), None, None) == -1
+    bad = _abi.Map.from_buffer_copy(m)
+    bad.n[1] = 0
+    assert L.rs_magnification(ctypes.c_void_p(0x1000), ctypes.byref(g), ctypes.byref(bad), ctypes.c_void_p(0x2000),
+                              None, None) == -1
+    bad = _abi.RayGrid.from_buffer_copy(g)
+    bad.hi[0] = bad.lo[0]
+    assert L.rs_magnification(ctypes.c_void_p(0x1000), ctypes.byref(bad), ctypes.byref(m), ctypes.c_void_p(0x2000),
+                              None, None) == -1
+    big = _abi.Map.from_buffer_copy(m)
+    big.n[0], big.n[1] = 65536, 32768
+    assert L.rs_magnification(ctypes.c_void_p(0x1000), ctypes.byref(g), ctypes.byref(big), ctypes.c_void_p(0x2000),
+                              None, None) == -2
+
+
 def test_version_string():
     P, L = _lib()
     assert b"gfx950" in L.rs_version()

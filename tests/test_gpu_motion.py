@@ -1,4 +1,4 @@
-"""GPU tests of moving lenses (section 5: stars move between frames).
+"""GPU tests of moving lenses (section 4: stars move between frames).
 
 Bars: advanced lens records bit-identical to the oracle's (FP64 motion, float32 rounding on
 both sides); a job with velocities and a time gives exactly the counts of the same job shot on

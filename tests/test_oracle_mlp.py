@@ -110,3 +110,23 @@ def test_training_fits_a_smooth_residual():
     l0 = mlp.loss(p0, u, t)
     p = mlp.train(p0, u, t, steps=400, batch=128, lr=1e-2)
     assert mlp.loss(p, u, t) < 2e-3 * l0
+
+
+def test_training_sample_schedule():
+    # Step t takes samples [(t - 1) B mod N, + B).  With W3 = 0 the output is b3, so the gradient of
+    # b3_1 is b3_1 - mean(target) over the batch; targets equal to the sample index and a zero
+    # learning rate (the parameters never move) read the batch of every step off the gradients.
+    n, batch, steps = 512, 128, 9
+    u = np.zeros((n, 2))
+    t = np.stack([np.arange(n, dtype=float), np.zeros(n)], 1)
+    p0 = np.zeros(mlp.N_PARAMS)
+    rec = []
+    p = mlp.train(p0, u, t, steps=steps, batch=batch, lr=0.0, record=rec)
+    assert np.array_equal(p, p0) and [s for s, _ in rec] == list(range(1, steps + 1))
+    for s, g in rec:
+        start = ((s - 1) * batch) % n
+        assert g[mlp.OFF_B3] == -(start + (batch - 1) / 2), (s, g[mlp.OFF_B3])
+        assert g[mlp.OFF_B3 + 1] == 0.0
+    # the cosine schedule reaches zero after the last step and is never negative
+    assert mlp.lr_at(1.0, steps + 1, steps) == 0.0
+    assert all(mlp.lr_at(1.0, s, steps) >= 0 for s in range(1, steps + 1))

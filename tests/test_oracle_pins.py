@@ -248,6 +248,22 @@ def test_smooth_sheet_exact_pixel_counts(kappa_c, gamma):
     assert counts.sum() + lost == w.n_rays
 
 
+def test_n_av_is_unlensed_rays_per_pixel():
+    # eq. 4: N_av is the number of rays a pixel receives without lensing, so with no lenses and no
+    # macro term every pixel whose edges fall on ray-cell edges holds exactly N_av rays (mu = 1);
+    # under a smooth sheet y = x / 2 (kappa_c = 1/2) a pixel's preimage is twice as wide per axis,
+    # so it receives 4 N_av rays and mu = 1 / lambda^2 = 4 exactly
+    w = _wl(np.zeros((0, 4)), 0.0, 0.0, (-1.0, -1.5), (1.0, 1.5), (64, 48), (-1.0, -1.5), (1.0, 1.5), (16, 12))
+    counts, lost = oracle.shoot(w)
+    assert oracle.n_av(w) == 16.0 and lost == 0
+    assert np.array_equal(counts, np.full((12, 16), 16, np.uint32))
+    assert np.array_equal(counts / oracle.n_av(w), np.ones((12, 16)))
+    w = _wl(np.zeros((0, 4)), 0.5, 0.0, (-2.0, -2.0), (2.0, 2.0), (128, 128), (-1.0, -1.0), (1.0, 1.0), (16, 16))
+    counts, lost = oracle.shoot(w)
+    assert oracle.n_av(w) == 16.0
+    assert np.array_equal(counts / oracle.n_av(w), np.full((16, 16), 4.0))
+
+
 # ---------------------------------------------------------------- random fields
 
 def test_mean_magnification_identity():

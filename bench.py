@@ -26,7 +26,6 @@ if ROOT not in sys.path:
 METRIC = "ray·lens interactions/s & Gflop/s; rays/s surrogate vs direct at ≤1% map err"
 FLOP_PER_INTERACTION = 10
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak (packed FMA)
-PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
@@ -53,7 +52,10 @@ def parse():
                     help="default workload: skip the light-curve, batched and learned far-field measurements")
     ap.add_argument("--legs", default="light_curves,zoom,frames,batched,farfield,large",
                     help="default workload: comma-separated extra measurements to run after the plain one")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0,
+                    help="target wall time of the oracle sample on the host threads (at most 2^22 rays)")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only run the issue-rate probes and print the direct sum's instruction-mix ceiling")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -91,6 +93,48 @@ def measured_traffic(workload_name: str, opts) -> float | None:
     return float(rec["hbm_bytes_per_launch"])
 
 
+PROBES = {"fmac_f32": 0, "fma_f32": 1, "mul_f32": 2, "rcp_f32": 3, "mix_13fmac_1rcp": 4, "add_f64": 5}
+
+
+def issue_rates(P):
+    """Lane instructions per second of each issue-rate probe (rs_probe_issue_rate)."""
+    import ctypes
+    import torch
+    L = P.lib()
+    out = {}
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for name, op in PROBES.items():
+        r, sec = ctypes.c_double(), ctypes.c_double()
+        P._check(L.rs_probe_issue_rate(op, ctypes.byref(r), ctypes.byref(sec), stream))
+        out[name] = r.value
+    return out
+
+
+def mix_ceiling(rates: dict, opts) -> dict | None:
+    """Instruction-mix ceiling of the direct sum's lens loop: the loop's instructions per interaction
+    (counted in this build's gfx950 assembly, profiles/k_direct_isa_mix.json, valid while direct.hip
+    is unchanged) priced at the probe rates.  A reciprocal costs what it adds to a 13 : 1 mix of
+    v_fmac_f32 and v_rcp_f32 (the lens loop's own proportion), 14 / R_mix - 13 / R_fmac."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_direct_isa_mix.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    cols, rows = (opts.block_cols or 1), (opts.block_rows or 4)
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or f"{cols}x{rows}" != rec["block"] \
+            or (opts.fp32_run or 16) != rec["fp32_run"] or (opts.lens_tile or 256) != rec["lens_tile"]:
+        return None
+    k = rec["per_interaction"]
+    rcp_cost = 14.0 / rates["mix_13fmac_1rcp"] - 13.0 / rates["fmac_f32"]
+    t = (k["vop2_f32"] / rates["fmac_f32"] + k["vop3_f32"] / rates["fma_f32"] + k["rcp_f32"] * rcp_cost
+         + (k["cvt_f64"] + k["add_f64"]) / rates["add_f64"])
+    return {"interactions_per_s": 1.0 / t, "tflops_10flop": FLOP_PER_INTERACTION / t / 1e12,
+            "per_interaction": {n: k[n] for n in ("vop2_f32", "vop3_f32", "rcp_f32", "cvt_f64", "add_f64")},
+            "rcp_cost_in_fmac_slots": rcp_cost * rates["fmac_f32"],
+            "isa_source": "profiles/k_direct_isa_mix.json"}
+
+
 def workload(name):
     import synth
     if name == "small":
@@ -98,25 +142,37 @@ def workload(name):
     return synth.workload_paper()
 
 
-def cpu_baseline(w, target_cpu_s: float):
-    """The FP64 oracle on a bounded sample of the same workload (rays drawn with the counter hash)."""
+def cpu_baseline(w, target_wall_s: float, gpu_pix=None):
+    """The FP64 oracle on a bounded sample of the same workload (rays drawn with the counter hash),
+    timed on the host threads; with the GPU's per-ray pixels of the whole grid (gpu_pix) the same
+    sample also gives the counted pixel-switch fraction of the benchmark's own launch."""
     import oracle
     import synth
     threads = max(1, min(16, os.cpu_count() or 1))
-    # calibrate on a tiny sample, then size the real one to ~target_cpu_s of CPU time
-    probe = synth.sample_indices(99, w.n_rays, 256)
+    # calibrate on a small sample, then size the real one to ~target_wall_s on `threads` threads,
+    # at most 2^22 rays (the parity sample of the paper-scale test)
+    probe = synth.sample_indices(99, w.n_rays, 2048)
     t0 = time.perf_counter()
-    oracle.trace(w, probe)
-    per_ray = max(1e-7, (time.perf_counter() - t0) / len(probe))
-    n = int(min(w.n_rays, max(threads, target_cpu_s / per_ray)))
-    idx = synth.sample_indices(100, w.n_rays, n)
+    oracle.trace_parallel(w, probe, threads=threads)
+    per_ray = max(1e-9, (time.perf_counter() - t0) / len(probe))
+    n = int(min(w.n_rays, 1 << 22, max(threads, target_wall_s / per_ray)))
+    idx = synth.sample_indices(12, w.n_rays, n)
     t0 = time.perf_counter()
-    oracle.trace_parallel(w, idx, threads=threads)
+    _, p_o = oracle.trace_parallel(w, idx, threads=threads)
     dt = time.perf_counter() - t0
     inter = len(idx) * w.n_lens
-    return {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+    base = {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} rays drawn by counter hash from the {w.name} grid x all {w.n_lens} lenses, "
                       f"FP64 single-threaded oracle on {threads} threads, {dt:.1f} s wall"}
+    parity = None
+    if gpu_pix is not None:
+        g = gpu_pix[idx].astype(np.int64)
+        diff = int(np.sum(g != p_o))
+        inmap = int(np.sum((g >= 0) | (p_o >= 0)))
+        parity = {"rays_checked": int(len(idx)), "rays_in_map": inmap, "rays_switched": diff,
+                  "switch_fraction": diff / max(1, inmap), "bar": 1e-5,
+                  "reference": "FP64 oracle, same rays, pixel or lost outcome per ray"}
+    return base, parity
 
 
 def _time_batch(P, torch, wl, steps, warmup, cache=None):
@@ -213,6 +269,15 @@ def bench_batched(args, emit=True):
     if emit:
         print(json.dumps(out), flush=True)
     return out
+
+
+def rebinned_p99(cs, cp, k=4):
+    """99th percentile of |N_s - N_p| / N_p over the pixels of k x k-rebinned maps with N_p > 0."""
+    h, w_ = (cs.shape[0] // k) * k, (cs.shape[1] // k) * k
+    rs = cs[:h, :w_].reshape(h // k, k, w_ // k, k).sum((1, 3))
+    rp = cp[:h, :w_].reshape(h // k, k, w_ // k, k).sum((1, 3))
+    m = rp > 0
+    return float(np.percentile(np.abs(rs[m] - rp[m]) / rp[m], 99)) if m.any() else 0.0
 
 
 def bench_surrogate(args, which=None, emit=True):
@@ -340,6 +405,9 @@ def bench_surrogate(args, which=None, emit=True):
                   "frozen_closure_l1_last_frame": float(np.abs(m_sur - m_mpl).sum() / max(1, m_mpl.sum()))}
     l1 = float(np.abs(m_sur - m_pl).sum() / max(1, m_pl.sum()))
     l1_aff = float(np.abs(m_aff - m_pl).sum() / max(1, m_pl.sum()))
+    shape = (w.map_n[1], w.map_n[0])
+    p99 = rebinned_p99(m_sur.reshape(shape), m_pl.reshape(shape))
+    p99_aff = rebinned_p99(m_aff.reshape(shape), m_pl.reshape(shape))
     plain_rays_s = judge_rays / plain_s
     sur_rays_s = w.n_rays / eval_s
     e2e_rays_s = w.n_rays / (fit_s + eval_s)
@@ -356,6 +424,9 @@ def bench_surrogate(args, which=None, emit=True):
         # rays per tile at which shooting a tile plainly costs as much as fitting its closure
         "break_even_rays_per_tile": fit_s * plain_rays_s / n_tiles,
         "map_l1_rel_err": {"surrogate": l1, "affine_only": l1_aff, "tolerance": 0.01},
+        # per-pixel side of the tolerance: 99th percentile of |N_s - N_p| / N_p over the pixels of
+        # 4 x 4-rebinned maps that the plain sum reaches
+        "p99_pixel_rel_err_4x4": {"surrogate": p99, "affine_only": p99_aff},
     }
     if moving is not None:
         out["moving_frames"] = moving
@@ -480,6 +551,14 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+    if args.microbench:
+        import torch
+        import paper_0905_2453_amd as P
+        torch.cuda.set_device(0)
+        rates = issue_rates(P)
+        print(json.dumps({"issue_rates_lane_ops_per_s": rates,
+                          "mix_ceiling_1x4": mix_ceiling(rates, P.Opts())}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in the design notes but not implemented", file=sys.stderr)
@@ -499,6 +578,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = workload(args.workload)
+    w.jitter_seed = args.jitter_seed
     lenses = torch.from_numpy(w.lenses).to(dev)
     counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
     lost = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -564,9 +644,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(w.name, opts),
                      "kernel": "k_direct", "flop_per_interaction": FLOP_PER_INTERACTION,
-                     "kernel_ms": kernel_s * 1e3,
-                     "frac_of_nonpacked_peak": achieved_tf / PEAK_FP32_NONPACKED_TFLOPS},
+                     "kernel_ms": kernel_s * 1e3},
     }
+    # the measured instruction-mix ceiling of the lens loop (issue-rate probes x counted mix)
+    rates = issue_rates(P)
+    ceil = mix_ceiling(rates, opts)
+    out["roofline"]["issue_rates_lane_ops_per_s"] = rates
+    if ceil is not None:
+        ceil["frac_achieved"] = (inter / kernel_s) / ceil["interactions_per_s"]
+        out["roofline"]["mix_ceiling"] = ceil
     legs = [] if args.workload != "paper" or args.plain_only else args.legs.split(",")
     if "light_curves" in legs:
         print("bench.py: plain direct sum done; light curves next", file=sys.stderr, flush=True)
@@ -594,12 +680,24 @@ def main():
             r = bench_surrogate(args, which=which, emit=False)
             out[f"surrogate_{which}"] = {k: r[k] for k in ("config", "fit_s", "eval_s", "plain_s_on_judged_tiles",
                                                             "rays_per_s", "speedup_vs_plain",
-                                                            "break_even_rays_per_tile", "map_l1_rel_err")}
+                                                            "break_even_rays_per_tile", "map_l1_rel_err",
+                                                            "p99_pixel_rel_err_4x4")}
             if "moving_frames" in r:
                 out[f"surrogate_{which}"]["moving_frames"] = r["moving_frames"]
     if not args.no_cpu_baseline:
-        print("bench.py: CPU oracle baseline next", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        print("bench.py: CPU oracle baseline and counted parity next", file=sys.stderr, flush=True)
+        # one more launch of the timed configuration with per-ray dumps (the map is unchanged by them)
+        rp = torch.empty(w.n_rays, dtype=torch.int32, device=dev)
+        ry = torch.empty((w.n_rays, 2), dtype=torch.float64, device=dev)
+        dopts = P.Opts.from_buffer_copy(opts)
+        dopts.ray_y, dopts.ray_pix = ry.data_ptr(), rp.data_ptr()
+        counts.zero_()
+        lost.zero_()
+        P.shoot_job(job, ws, dopts, stream)
+        torch.cuda.synchronize()
+        pix = rp.cpu().numpy()
+        del ry, rp
+        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_seconds, pix)
     print(json.dumps(out), flush=True)
 
 

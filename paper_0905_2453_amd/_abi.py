@@ -109,6 +109,8 @@ EXPORTS = [
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("rs_release_graphs", None, []),
+    ("rs_probe_issue_rate", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
 ]
 
 

@@ -35,15 +35,27 @@ constexpr float kPadCoord = 1.0e18f;
 __device__ __forceinline__ uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+using bf16x2 = __bf16 __attribute__((ext_vector_type(2)));
+using f32x2 = float __attribute__((ext_vector_type(2)));
+
+// two floats -> a bfloat16 pair (a in the low half), round to nearest even (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pk2(float a, float b)
+{
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float lo_bf16(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float hi_bf16(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
 __device__ __forceinline__ bf16x8 lds8(const uint16_t *p)
 {
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p));
 }
-__device__ __forceinline__ bf16x8 pack8(const uint16_t *a)
+// four bfloat16 pairs -> the 8-element MFMA operand (pair j gives elements 2j, 2j + 1)
+__device__ __forceinline__ bf16x8 pack4(const uint32_t *p)
 {
-    u16x8 v;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = a[i];
+    const u32x4 v = {p[0], p[1], p[2], p[3]};
     return __builtin_bit_cast(bf16x8, v);
 }
 
@@ -105,46 +117,65 @@ __device__ __forceinline__ uint16_t *tile_w(const FarArgs &f, uint32_t tile)
 }
 
 // Features of one axis for a lane: phi[8 hf + 2k] = sin(w_k u), phi[8 hf + 2k + 1] = cos(w_k u),
-// w_k = (pi / 2) 2^k, rounded to bfloat16.  w_k u is 2 pi (2^(k-2) u), an exact scaling of u,
-// so each value is one hardware sine or cosine of an argument in revolutions (|2^(k-2) u| <= 2).
-__device__ __forceinline__ void features8(float u, uint16_t *out)
+// w_k = (pi / 2) 2^k, rounded to bfloat16 (pair k of out: sine low, cosine high).  w_k u is
+// 2 pi (2^(k-2) u), an exact scaling of u, so each value is one hardware sine or cosine of an
+// argument in revolutions (|2^(k-2) u| <= 2).
+__device__ __forceinline__ void features8(float u, uint32_t *out)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float rev = u * (float)(1 << k) * 0.25f;
-        out[2 * k] = to_bf16(__builtin_amdgcn_sinf(rev));
-        out[2 * k + 1] = to_bf16(__builtin_amdgcn_cosf(rev));
+        out[k] = pk2(__builtin_amdgcn_sinf(rev), __builtin_amdgcn_cosf(rev));
     }
 }
 
 // Forward pass of 32 samples (one per lane pair) through layers 1 and 2: returns the bfloat16
 // activations h1, h2 in the slot layout and the network output (both lanes); with TRAIN also
-// the SiLU derivatives silu'(z) = s (1 + z (1 - s)), s = sigmoid(z), that the backward pass needs.
+// the SiLU derivatives silu'(z) = s (1 + z (1 - s)) = s + h (1 - s), s = sigmoid(z), h = z s,
+// that the backward pass needs.  Activations are kept as bfloat16 pairs: word j holds slot 2j in
+// its low half and slot 2j + 1 in its high half, which is the B-operand layout of the next MFMA.
 struct Fwd {
     float d1[32], d2[32];
-    uint16_t h1[32], h2[32];
+    uint32_t h1[16], h2[16];
     float o[2];
 };
 
+// Eight consecutive hidden units' layer-3 weights of output row o (16-byte LDS read).
+__device__ __forceinline__ u16x8 w3_row8(const uint16_t *Wbf, int o, int g, int hf)
+{
+    return *reinterpret_cast<const u16x8 *>(Wbf + kOffW3 + 64 * o + 16 * g + 8 * hf);
+}
+
 template <bool TRAIN>
-__device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint16_t *phi8, int lane,
+__device__ __forceinline__ void activate16(const f32x16 &acc, const float *bias, int T, int hf, float *d, uint32_t *h)
+{
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+        const float za = acc[q] + bias[slot_unit(16 * T + q, hf)];
+        const float zb = acc[q + 1] + bias[slot_unit(16 * T + q + 1, hf)];
+        const float sa = sigm(za), sb = sigm(zb);
+        const float ha = za * sa, hb = zb * sb;
+        if (TRAIN) {
+            d[16 * T + q] = fmaf(ha, 1.0f - sa, sa);
+            d[16 * T + q + 1] = fmaf(hb, 1.0f - sb, sb);
+        }
+        h[(16 * T + q) / 2] = pk2(ha, hb);
+    }
+}
+
+template <bool TRAIN>
+__device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint32_t *phi4, int lane,
                                           Fwd &r)
 {
     const int hf = lane >> 5, col = lane & 31;
-    const bf16x8 bphi = pack8(phi8);
+    const bf16x8 bphi = pack4(phi4);
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
         const int R = 32 * T + col;
         const bf16x8 a = lds8(Wbf + kOffW1 + perm_row(R) * 16 + 8 * hf);
         f32x16 acc = {};
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bphi, acc, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const float z = acc[q] + sbias[slot_unit(16 * T + q, hf)];
-            const float sg = sigm(z);
-            if (TRAIN) r.d1[16 * T + q] = sg * (1.0f + z * (1.0f - sg));
-            r.h1[16 * T + q] = to_bf16(z * sg);
-        }
+        activate16<TRAIN>(acc, sbias, T, hf, r.d1, r.h1);
     }
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
@@ -153,23 +184,22 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const bf16x8 a = lds8(Wbf + kOffW2 + perm_row(R) * 64 + 16 * kk + 8 * hf);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(r.h1 + 8 * kk), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(r.h1 + 4 * kk), acc, 0, 0, 0);
         }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const float z = acc[q] + sbias[64 + slot_unit(16 * T + q, hf)];
-            const float sg = sigm(z);
-            if (TRAIN) r.d2[16 * T + q] = sg * (1.0f + z * (1.0f - sg));
-            r.h2[16 * T + q] = to_bf16(z * sg);
-        }
+        activate16<TRAIN>(acc, sbias + 64, T, hf, r.d2, r.h2);
     }
+    // layer 3 on the VALU: slots 8 g .. 8 g + 7 are the consecutive units 16 g + 8 hf + e
     float po0 = 0.f, po1 = 0.f;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-        const int u = slot_unit(q, hf);
-        const float h = from_bf16(r.h2[q]);
-        po0 = fmaf(from_bf16(Wbf[kOffW3 + u]), h, po0);
-        po1 = fmaf(from_bf16(Wbf[kOffW3 + 64 + u]), h, po1);
+    for (int g = 0; g < 4; ++g) {
+        const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t p = r.h2[4 * g + e / 2];
+            const float h = (e & 1) ? hi_bf16(p) : lo_bf16(p);
+            po0 = fmaf(from_bf16(w0[e]), h, po0);
+            po1 = fmaf(from_bf16(w1[e]), h, po1);
+        }
     }
     // the two halves of a sample live in lanes l and l ^ 32; add them in a fixed order
     const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
@@ -468,22 +498,27 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
             const int si = i0 + 32 * (4 * rd + wave) + col;
             const float u = f.samples[2 * si + hf];
             const float t0 = tgt[2 * si], t1 = tgt[2 * si + 1];
-            uint16_t phi8[8];
-            features8(u, phi8);
+            uint32_t phi4[4];
+            features8(u, phi4);
             Fwd fw;
-            forward32<true>(Wbf, sbias, phi8, lane, fw);
+            forward32<true>(Wbf, sbias, phi4, lane, fw);
             const float inv_b = 1.0f / (float)f.batch;
             const float d30 = (fw.o[0] - t0) * inv_b, d31 = (fw.o[1] - t1) * inv_b;
-            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3
-            uint16_t dz2[32];
+            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 (bfloat16 pairs like the activations)
+            uint32_t dz2[16];
 #pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int un = slot_unit(q, hf);
-                const float dh = fmaf(from_bf16(Wbf[kOffW3 + un]), d30, from_bf16(Wbf[kOffW3 + 64 + un]) * d31);
-                dz2[q] = to_bf16(dh * fw.d2[q]);
+            for (int g = 0; g < 4; ++g) {
+                const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
+#pragma unroll
+                for (int e = 0; e < 8; e += 2) {
+                    const int q = 8 * g + e;
+                    const float dha = fmaf(from_bf16(w0[e]), d30, from_bf16(w1[e]) * d31);
+                    const float dhb = fmaf(from_bf16(w0[e + 1]), d30, from_bf16(w1[e + 1]) * d31);
+                    dz2[q / 2] = pk2(dha * fw.d2[q], dhb * fw.d2[q + 1]);
+                }
             }
             // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
-            uint16_t dz1[32];
+            uint32_t dz1[16];
 #pragma unroll
             for (int T = 0; T < 2; ++T) {
                 const int R = 32 * T + col;
@@ -491,22 +526,30 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const bf16x8 a = lds8(W2T + perm_row(R) * 64 + 16 * kk + 8 * hf);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack8(dz2 + 8 * kk), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(dz2 + 4 * kk), acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) dz1[16 * T + q] = to_bf16(acc[q] * fw.d1[16 * T + q]);
+                for (int q = 0; q < 16; q += 2)
+                    dz1[(16 * T + q) / 2] = pk2(acc[q] * fw.d1[16 * T + q], acc[q + 1] * fw.d1[16 * T + q + 1]);
             }
             // stage [unit][sample] copies for the weight gradients
 #pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int un = slot_unit(q, hf);
-                z2s[un * 32 + col] = dz2[q];
-                h1s[un * 32 + col] = fw.h1[q];
-                z1s[un * 32 + col] = dz1[q];
-                h2s[un * 32 + col] = fw.h2[q];
+            for (int j = 0; j < 16; ++j) {
+                const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
+                z2s[ua * 32 + col] = (uint16_t)dz2[j];
+                z2s[ub * 32 + col] = (uint16_t)(dz2[j] >> 16);
+                h1s[ua * 32 + col] = (uint16_t)fw.h1[j];
+                h1s[ub * 32 + col] = (uint16_t)(fw.h1[j] >> 16);
+                z1s[ua * 32 + col] = (uint16_t)dz1[j];
+                z1s[ub * 32 + col] = (uint16_t)(dz1[j] >> 16);
+                h2s[ua * 32 + col] = (uint16_t)fw.h2[j];
+                h2s[ub * 32 + col] = (uint16_t)(fw.h2[j] >> 16);
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) phs[(8 * hf + i) * 32 + col] = phi8[i];
+            for (int k = 0; k < 4; ++k) {
+                phs[(8 * hf + 2 * k) * 32 + col] = (uint16_t)phi4[k];
+                phs[(8 * hf + 2 * k + 1) * 32 + col] = (uint16_t)(phi4[k] >> 16);
+            }
             if (hf == 0) {
                 d3s[col] = d30;
                 d3s[32 + col] = d31;
@@ -595,7 +638,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         const float ibc1 = (float)(1.0 / (1.0 - b1t)), ibc2 = (float)(1.0 / (1.0 - b2t));
         // thread tid owns parameters tid + 256 k, taken eight at a time: the eight parameters'
         // optimiser state is loaded before any of it is used, so the global round trips overlap
-        constexpr int kPer = (kNParams + 255) / 256, kChunk = 8;
+        constexpr int kPer = (kNParams + 255) / 256, kChunk = kPer;
         const float *gw = reinterpret_cast<const float *>(sstage);
 #pragma unroll 1
         for (int k0 = 0; k0 < kPer; k0 += kChunk) {
@@ -805,10 +848,10 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
         float o0 = 0.f, o1 = 0.f;
         if (!f.affine_only) {
             const float u = hf == 0 ? (float)(((double)x1 - c[0]) / hw[0]) : (float)(((double)x2 - c[1]) / hw[1]);
-            uint16_t phi8[8];
-            features8(u, phi8);
+            uint32_t phi4[4];
+            features8(u, phi4);
             Fwd fw;
-            forward32<false>(Wbf, sbias, phi8, lane, fw);
+            forward32<false>(Wbf, sbias, phi4, lane, fw);
             o0 = fw.o[0];
             o1 = fw.o[1];
         }

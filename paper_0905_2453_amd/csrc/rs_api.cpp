@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rs_internal.h"
+#include "rs_probe.h"
 
 namespace {
 
@@ -1182,6 +1183,40 @@ int rs_light_curve(const uint32_t *counts, const rs_map *map, double n_av, const
     a.frame_stride = frame_stride;
     const hipError_t e = rs::launch_light_curve(a, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RS_OK : dev_fail(e, "light-curve launch");
+}
+
+int rs_probe_issue_rate(int op, double *lane_ops_per_s, double *seconds, void *stream)
+{
+    g_err[0] = '\0';
+    if (op < RS_PROBE_FMAC_F32 || op > RS_PROBE_ADD_F64) return fail(RS_EINVAL, "unknown probe %d", op);
+    if (!lane_ops_per_s) return fail(RS_EINVAL, "lane_ops_per_s is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return dev_fail(e, "device query");
+    // 8 workgroups of 4 waves per compute unit: 8 waves per SIMD, enough to hide every latency
+    const int blocks = 8 * cus;
+    // about 20 ms per launch at the measured rates (reciprocals and FP64 adds issue slower)
+    const int iters = (op == RS_PROBE_RCP_F32 || op == RS_PROBE_ADD_F64) ? 2048 : 8192;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e == hipSuccess) e = rs::launch_probe(op, blocks, iters, s);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(t0, s);
+    if (e == hipSuccess) e = rs::launch_probe(op, blocks, iters, s);
+    if (e == hipSuccess) e = hipEventRecord(t1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return dev_fail(e, "probe launch");
+    if (!(ms > 0.f)) return fail(RS_EDEVICE, "probe timing gave %g ms", (double)ms);
+    const double ops = (double)blocks * 256.0 * (double)iters * (double)rs::probe_ops_per_iter(op);
+    *lane_ops_per_s = ops / (1e-3 * (double)ms);
+    if (seconds) *seconds = 1e-3 * (double)ms;
+    return RS_OK;
 }
 
 void rs_release_graphs(void)

@@ -229,6 +229,9 @@ hipError_t launch_reduce(const uint32_t *partial, int64_t bins, int64_t pstride,
                          hipStream_t s);
 // mu[b] = counts[b] / n_av for b < bins (FP64).
 hipError_t launch_magnification(const uint32_t *counts, int64_t bins, double n_av, double *mu, hipStream_t s);
+// Issue-rate probes (rs_probe.h): lane instructions per loop iteration of probe `op`, and one launch.
+int probe_ops_per_iter(int op);
+hipError_t launch_probe(int op, int blocks, int iters, hipStream_t s);
 // Device address of the fixed scratch array (kNoAllocWords words) on the current device, looked up
 // with hipGetSymbolAddress on the first call per device.
 hipError_t noalloc_scratch(uint32_t **ptr);

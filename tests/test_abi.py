@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rs.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
 
 
 def _lib():
@@ -21,9 +22,11 @@ def _lib():
 
 
 def _declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(rs_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rs_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_functions_exported():
@@ -234,6 +237,14 @@ def test_magnification_validation_and_n_av_without_device():
     big.n[0], big.n[1] = 65536, 32768
     assert L.rs_magnification(ctypes.c_void_p(0x1000), ctypes.byref(g), ctypes.byref(big), ctypes.c_void_p(0x2000),
                               None, None) == -2
+
+
+def test_probe_validation_without_device():
+    P, L = _lib()
+    r = ctypes.c_double()
+    assert L.rs_probe_issue_rate(99, ctypes.byref(r), None, None) == -1
+    assert L.rs_probe_issue_rate(-1, ctypes.byref(r), None, None) == -1
+    assert L.rs_probe_issue_rate(0, None, None, None) == -1
 
 
 def test_version_string():

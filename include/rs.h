@@ -255,7 +255,7 @@ typedef struct {
     double r_near;              /* near radius (Einstein radii), e.g. 8                            */
     int32_t n_samples;          /* fit samples per tile, multiple of 1024, e.g. 4096                */
     int32_t steps;              /* Adam steps (0 = keep the initial parameters), e.g. 2000          */
-    int32_t batch;              /* samples per step: multiple of 128 dividing n_samples, e.g. 512   */
+    int32_t batch;              /* samples per step: multiple of 256 dividing n_samples, e.g. 512   */
     float lr;                   /* peak learning rate, e.g. 1e-2                                    */
     double cell_size;           /* lens cell side for the near-set search (0 = r_near / 4)          */
     const float *samples;       /* device, n_samples x 2 tile-local points in [-1,1]^2 (input)       */

@@ -438,11 +438,19 @@ __global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
 
 // ---------------------------------------------------------------- fit: training
 
-// One workgroup (4 waves) trains one tile's network with mini-batch Adam.  Each wave takes
-// 32-sample chunks; per chunk: forward, output delta, backward through layers 2 and 1, then the
-// weight gradients contract over the chunk's samples through LDS.  The four waves' gradients
-// are summed in a fixed order, then every thread updates its share of the parameters (FP32
-// master weights in global memory; Adam moments and the bfloat16 copies in LDS).
+// One workgroup of 8 waves (two per SIMD, so that one wave's MFMA, LDS and transcendental
+// latencies hide behind the other's work) trains one tile's network with mini-batch Adam.  A step
+// takes its batch in rounds of 256 samples, 32 per wave.  In a round every wave runs the forward
+// and backward pass of its own samples (a lane pair per sample, as in the evaluation) and stages
+// [unit][sample] bfloat16 copies of dz2, h1, dz1 and h2 and the features in LDS; after a
+// workgroup barrier each wave contracts the blocks of the weight gradients it owns over all 256
+// samples (16x16x32 MFMAs): the dW2 blocks of rows 16 (w / 2) .. + 16 and columns 32 (w % 2) .. + 32,
+// and the dW1 rows 16 (w % 4) .. + 16 over the samples of waves 4 (w / 4) .. + 3.  Bias and
+// layer-3 gradients are summed by each wave over its own samples (lane = hidden unit).  After the
+// last round the partial sums are exchanged through LDS in a fixed order and each parameter is
+// updated by the lane that owns its gradient: FP32 master weights and Adam moments live in the fit
+// workspace (64.5 KB per tile, read and written once per step: the working set of the tiles in
+// flight stays in L2), the bfloat16 weight copies the MFMAs read and the FP32 biases in LDS.
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -450,30 +458,34 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
+constexpr int kTrainWaves = 8;
+constexpr int kTrainThreads = 64 * kTrainWaves;
+constexpr int kRoundSamples = 32 * kTrainWaves;
+constexpr int kStageWords = 64 * 32;   // one [unit][sample] bfloat16 array of one wave
+
+__global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
 {
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
     __shared__ float sbias[130];
-    __shared__ float red[kNParams];
-    __shared__ float adam_m[kNParams], adam_v[kNParams];   // Adam moments (the master weights stay in global memory)
-    // per wave: [unit][sample] staging of dz2, h1, dz1 and h2 (4 x 64 x 32 bfloat16 each); after
-    // a step's last round the same 64 KB hold waves 1-3's gradients for the reduction
-    __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * 4 * 64 * 32];
-    static_assert(3 * kNParams * sizeof(float) <= sizeof(sstage), "gradient scratch");
-    __shared__ __attribute__((aligned(16))) uint16_t sphi[4][16 * 32];
-    __shared__ float sd3[4][2 * 32];
+    // array a (0 dz2, 1 h1, 2 dz1, 3 h2) of wave v at sstage + (a kTrainWaves + v) kStageWords
+    __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * kTrainWaves * kStageWords];
+    __shared__ __attribute__((aligned(16))) uint16_t sphi[kTrainWaves][16 * 32];
+    __shared__ float sd3[kTrainWaves][2 * 32];
 
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
-    float *state = f.state + (size_t)tile * kNParams;  // FP32 master weights
+    const int l16 = lane & 15, l4 = lane >> 4;
+    float *mw = f.state + (size_t)tile * 3 * kNParams;   // FP32 master weights, Adam m, Adam v
+    float *am = mw + kNParams, *av = am + kNParams;
     const float *tgt = f.targets + (size_t)tile * f.n_samples * 2;
+    auto stg = [&](int a, int v) { return sstage + (a * kTrainWaves + v) * kStageWords; };
 
-    for (int p = tid; p < kNParams; p += 256) {
+    for (int p = tid; p < kNParams; p += kTrainThreads) {
         const float w = f.init_params[p];
-        state[p] = w;
-        adam_m[p] = 0.f;
-        adam_v[p] = 0.f;
+        mw[p] = w;
+        am[p] = 0.f;
+        av[p] = 0.f;
         const uint16_t b = to_bf16(w);
         Wbf[p] = b;
         if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
@@ -481,30 +493,84 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
         if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
     }
-    __syncthreads();
+    // (the first round's barrier orders these stores before their use)
 
-    const int rounds = f.batch / 128;
+    const int rounds = f.batch / kRoundSamples;
+    const float inv_b = 1.0f / (float)f.batch;
+    const int jb = wave >> 1, ib0 = 2 * (wave & 1);   // owned dW2 blocks: rows 16 jb, columns 16 ib0 .. + 32
+    const int t4 = wave & 3, vh = 4 * (wave >> 2);     // owned dW1 rows 16 t4, over waves vh .. vh + 3
+    uint16_t *z2s = stg(0, wave), *h1s = stg(1, wave), *z1s = stg(2, wave), *h2s = stg(3, wave);
+    uint16_t *phs = sphi[wave];
+    float *d3s = sd3[wave];
     double b1t = 1.0, b2t = 1.0;
     for (int step = 1; step <= f.steps; ++step) {
         const int i0 = (int)(((int64_t)(step - 1) * f.batch) % f.n_samples);
-        f32x16 g2[2][2] = {};
-        f32x4 g1[4] = {};
+        f32x4 g2[2] = {}, g1 = {};
         float gb1 = 0.f, gb2 = 0.f, gw30 = 0.f, gw31 = 0.f, gb3 = 0.f;
-        uint16_t *z2s = sstage + (0 * 4 + wave) * 2048, *h1s = sstage + (1 * 4 + wave) * 2048;
-        uint16_t *z1s = sstage + (2 * 4 + wave) * 2048, *h2s = sstage + (3 * 4 + wave) * 2048;
-        uint16_t *phs = sphi[wave];
-        float *d3s = sd3[wave];
         for (int rd = 0; rd < rounds; ++rd) {
-            const int si = i0 + 32 * (4 * rd + wave) + col;
+            // the staging area's readers of the previous round (or the last update's parameter
+            // copies) are done
+            __syncthreads();
+            const int si = i0 + kRoundSamples * rd + 32 * wave + col;
             const float u = f.samples[2 * si + hf];
             const float t0 = tgt[2 * si], t1 = tgt[2 * si + 1];
             uint32_t phi4[4];
             features8(u, phi4);
-            Fwd fw;
-            forward32<true>(Wbf, sbias, phi4, lane, fw);
-            const float inv_b = 1.0f / (float)f.batch;
-            const float d30 = (fw.o[0] - t0) * inv_b, d31 = (fw.o[1] - t1) * inv_b;
-            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 (bfloat16 pairs like the activations)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                phs[(8 * hf + 2 * k) * 32 + col] = (uint16_t)phi4[k];
+                phs[(8 * hf + 2 * k + 1) * 32 + col] = (uint16_t)(phi4[k] >> 16);
+            }
+            // forward: layer 1, layer 2 (each staged as soon as it is computed), layer 3
+            float d1[32], d2[32];
+            uint32_t h1[16], h2[16];
+            const bf16x8 bphi = pack4(phi4);
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+                const bf16x8 a = lds8(Wbf + kOffW1 + perm_row(32 * T + col) * 16 + 8 * hf);
+                f32x16 acc = {};
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bphi, acc, 0, 0, 0);
+                activate16<true>(acc, sbias, T, hf, d1, h1);
+            }
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+                f32x16 acc = {};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const bf16x8 a = lds8(Wbf + kOffW2 + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(h1 + 4 * kk), acc, 0, 0, 0);
+                }
+                activate16<true>(acc, sbias + 64, T, hf, d2, h2);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
+                h1s[ua * 32 + col] = (uint16_t)h1[j];
+                h1s[ub * 32 + col] = (uint16_t)(h1[j] >> 16);
+                h2s[ua * 32 + col] = (uint16_t)h2[j];
+                h2s[ub * 32 + col] = (uint16_t)(h2[j] >> 16);
+            }
+            float po0 = 0.f, po1 = 0.f;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t pr = h2[4 * g + e / 2];
+                    const float h = (e & 1) ? hi_bf16(pr) : lo_bf16(pr);
+                    po0 = fmaf(from_bf16(w0[e]), h, po0);
+                    po1 = fmaf(from_bf16(w1[e]), h, po1);
+                }
+            }
+            const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
+            const float o0 = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
+            const float o1 = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
+            const float d30 = (o0 - t0) * inv_b, d31 = (o1 - t1) * inv_b;
+            if (hf == 0) {
+                d3s[col] = d30;
+                d3s[32 + col] = d31;
+            }
+            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3
             uint32_t dz2[16];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
@@ -514,68 +580,35 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                     const int q = 8 * g + e;
                     const float dha = fmaf(from_bf16(w0[e]), d30, from_bf16(w1[e]) * d31);
                     const float dhb = fmaf(from_bf16(w0[e + 1]), d30, from_bf16(w1[e + 1]) * d31);
-                    dz2[q / 2] = pk2(dha * fw.d2[q], dhb * fw.d2[q + 1]);
+                    dz2[q / 2] = pk2(dha * d2[q], dhb * d2[q + 1]);
                 }
             }
             // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
             uint32_t dz1[16];
 #pragma unroll
             for (int T = 0; T < 2; ++T) {
-                const int R = 32 * T + col;
                 f32x16 acc = {};
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
-                    const bf16x8 a = lds8(W2T + perm_row(R) * 64 + 16 * kk + 8 * hf);
+                    const bf16x8 a = lds8(W2T + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(dz2 + 4 * kk), acc, 0, 0, 0);
                 }
 #pragma unroll
                 for (int q = 0; q < 16; q += 2)
-                    dz1[(16 * T + q) / 2] = pk2(acc[q] * fw.d1[16 * T + q], acc[q + 1] * fw.d1[16 * T + q + 1]);
+                    dz1[(16 * T + q) / 2] = pk2(acc[q] * d1[16 * T + q], acc[q + 1] * d1[16 * T + q + 1]);
             }
-            // stage [unit][sample] copies for the weight gradients
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
                 z2s[ua * 32 + col] = (uint16_t)dz2[j];
                 z2s[ub * 32 + col] = (uint16_t)(dz2[j] >> 16);
-                h1s[ua * 32 + col] = (uint16_t)fw.h1[j];
-                h1s[ub * 32 + col] = (uint16_t)(fw.h1[j] >> 16);
                 z1s[ua * 32 + col] = (uint16_t)dz1[j];
                 z1s[ub * 32 + col] = (uint16_t)(dz1[j] >> 16);
-                h2s[ua * 32 + col] = (uint16_t)fw.h2[j];
-                h2s[ub * 32 + col] = (uint16_t)(fw.h2[j] >> 16);
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                phs[(8 * hf + 2 * k) * 32 + col] = (uint16_t)phi4[k];
-                phs[(8 * hf + 2 * k + 1) * 32 + col] = (uint16_t)(phi4[k] >> 16);
-            }
-            if (hf == 0) {
-                d3s[col] = d30;
-                d3s[32 + col] = d31;
-            }
-            // the staging areas are this wave's own: LDS operations of one wave complete in
-            // order, so a wave-scope fence (no workgroup barrier) orders the stores and loads
+            // this wave's own staging: a wave-scope fence orders its stores and loads
             wave_sync();
-            // dW2 += dz2^T h1 (K = 32 samples)
-#pragma unroll
-            for (int TA = 0; TA < 2; ++TA)
-#pragma unroll
-                for (int TB = 0; TB < 2; ++TB)
-#pragma unroll
-                    for (int kb = 0; kb < 2; ++kb) {
-                        const bf16x8 a = lds8(z2s + (32 * TA + col) * 32 + 16 * kb + 8 * hf);
-                        const bf16x8 b = lds8(h1s + (32 * TB + col) * 32 + 16 * kb + 8 * hf);
-                        g2[TA][TB] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, g2[TA][TB], 0, 0, 0);
-                    }
-            // dW1 += dz1^T phi (16x16x32: K = 32 samples)
-#pragma unroll
-            for (int T4 = 0; T4 < 4; ++T4) {
-                const bf16x8 a = lds8(z1s + (16 * T4 + (lane & 15)) * 32 + 8 * (lane >> 4));
-                const bf16x8 b = lds8(phs + (lane & 15) * 32 + 8 * (lane >> 4));
-                g1[T4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1[T4], 0, 0, 0);
-            }
-            // bias gradients and dW3: lane = hidden unit (16-byte loads, sums in sample order)
+            // bias gradients and dW3 over this wave's samples: lane = hidden unit (16-byte loads,
+            // sums in sample order)
             {
                 float s1 = 0.f, s2 = 0.f, w0 = 0.f, w1 = 0.f;
 #pragma unroll
@@ -602,33 +635,92 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
                     gb3 += s3;
                 }
             }
-            wave_sync();
+            __syncthreads();   // every wave's staging of this round is complete
+            // owned weight-gradient blocks, contracted over the round's samples in wave order
+#pragma unroll
+            for (int v = 0; v < kTrainWaves; ++v) {
+                const bf16x8 a = lds8(stg(0, v) + (16 * jb + l16) * 32 + 8 * l4);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const bf16x8 b = lds8(stg(1, v) + (16 * (ib0 + c) + l16) * 32 + 8 * l4);
+                    g2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g2[c], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const bf16x8 a = lds8(stg(2, vh + v) + (16 * t4 + l16) * 32 + 8 * l4);
+                const bf16x8 b = lds8(sphi[vh + v] + l16 * 32 + 8 * l4);
+                g1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1, 0, 0, 0);
+            }
         }
-        __syncthreads();   // every wave is past its last round before the staging area is reused
-        // every wave stores its gradients at once (wave 0 into red[], waves 1-3 into the staging
-        // area, free after the rounds); the Adam loop then adds them in wave order
+        // The lane's parameters: slots 0-7 dW2, 8-11 dW1 (waves 0-3), 12-15 the biases and layer-3
+        // weights of unit 8 w + lane (lanes 0-7), slot 12 b3 (wave 0, lanes 8 and 9); -1 = none.
+        // The lane index is passed through an empty asm statement so that these indices are
+        // recomputed here every step (a few integer operations) instead of being kept, or spilled,
+        // across the rounds.
+        int ln = lane, wv = wave;
+        asm volatile("" : "+v"(ln), "+v"(wv));
+        const int m16 = ln & 15, q4 = ln >> 4;
+        constexpr int kSlots = 16;
+        int pid[kSlots];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            pid[k] = kOffW2 + 64 * (16 * (wv >> 1) + 4 * q4 + (k & 3)) + 16 * (2 * (wv & 1) + (k >> 2)) + m16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pid[8 + r] = wv < 4 ? kOffW1 + 16 * (16 * (wv & 3) + 4 * q4 + r) + m16 : -1;
         {
-            float *gdst = wave == 0 ? red : reinterpret_cast<float *>(sstage) + (wave - 1) * kNParams;
+            const int un = 8 * wv + ln;
+            pid[12] = ln < 8 ? kOffB1 + un : (wv == 0 && ln < 10 ? kOffB3 + ln - 8 : -1);
+            pid[13] = ln < 8 ? kOffB2 + un : -1;
+            pid[14] = ln < 8 ? kOffW3 + un : -1;
+            pid[15] = ln < 8 ? kOffW3 + 64 + un : -1;
+        }
+        // the optimiser state of every slot is requested before the partial sums are exchanged, so
+        // its global round trip overlaps the exchange
+        float sw[kSlots], sm[kSlots], sv[kSlots];
 #pragma unroll
-            for (int TA = 0; TA < 2; ++TA)
+        for (int k = 0; k < kSlots; ++k) {
+            const uint32_t p = pid[k] < 0 ? 0u : (uint32_t)pid[k];
+            sw[k] = mw[p];
+            sm[k] = am[p];
+            sv[k] = av[p];
+        }
+        __syncthreads();   // the last round's readers are done: the staging area takes the partial sums
+        float *xb = reinterpret_cast<float *>(sstage);      // [wave][4][64]: gb1, gb2, gw30, gw31
+        float *x3 = xb + kTrainWaves * 4 * 64;               // [wave][2]: gb3
+        float *x1 = x3 + kTrainWaves * 2;                    // [wave - 4][lane][4]: dW1 partials of waves 4-7
+        xb[(wave * 4 + 0) * 64 + lane] = gb1;
+        xb[(wave * 4 + 1) * 64 + lane] = gb2;
+        xb[(wave * 4 + 2) * 64 + lane] = gw30;
+        xb[(wave * 4 + 3) * 64 + lane] = gw31;
+        if (lane < 2) x3[wave * 2 + lane] = gb3;
+        if (wave >= 4) {
 #pragma unroll
-                for (int TB = 0; TB < 2; ++TB)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int j = 32 * TA + 8 * (r >> 2) + 4 * hf + (r & 3), i = 32 * TB + col;
-                        gdst[kOffW2 + j * 64 + i] = g2[TA][TB][r];
-                    }
-#pragma unroll
-            for (int T4 = 0; T4 < 4; ++T4)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) gdst[kOffW1 + (16 * T4 + 4 * (lane >> 4) + r) * 16 + (lane & 15)] = g1[T4][r];
-            gdst[kOffB1 + lane] = gb1;
-            gdst[kOffB2 + lane] = gb2;
-            gdst[kOffW3 + lane] = gw30;
-            gdst[kOffW3 + 64 + lane] = gw31;
-            if (lane < 2) gdst[kOffB3 + lane] = gb3;
+            for (int r = 0; r < 4; ++r) x1[((wave - 4) * 64 + lane) * 4 + r] = g1[r];
         }
         __syncthreads();
+        float gr[kSlots];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gr[k] = g2[k >> 2][k & 3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gr[8 + r] = wave < 4 ? g1[r] + x1[(wave * 64 + lane) * 4 + r] : 0.f;
+        if (lane < 8) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float g = 0.f;
+#pragma unroll
+                for (int v = 0; v < kTrainWaves; ++v) g += xb[(v * 4 + k) * 64 + 8 * wave + lane];
+                gr[12 + k] = g;
+            }
+        } else {
+            float g = 0.f;
+            if (wave == 0 && lane < 10) {
+#pragma unroll
+                for (int v = 0; v < kTrainWaves; ++v) g += x3[v * 2 + lane - 8];
+            }
+            gr[12] = g;
+            gr[13] = gr[14] = gr[15] = 0.f;
+        }
         // Adam with bias correction and a cosine-decayed learning rate
         b1t *= 0.9;
         b2t *= 0.999;
@@ -636,50 +728,34 @@ __global__ void __launch_bounds__(256) k_mlp_train(const FarArgs f)
         // bias corrections as per-step reciprocals; the per-parameter quotient by the hardware
         // reciprocal (1 ulp, far below the bfloat16 rounding of the weights)
         const float ibc1 = (float)(1.0 / (1.0 - b1t)), ibc2 = (float)(1.0 / (1.0 - b2t));
-        // thread tid owns parameters tid + 256 k, taken eight at a time: the eight parameters'
-        // optimiser state is loaded before any of it is used, so the global round trips overlap
-        constexpr int kPer = (kNParams + 255) / 256, kChunk = kPer;
-        const float *gw = reinterpret_cast<const float *>(sstage);
-#pragma unroll 1
-        for (int k0 = 0; k0 < kPer; k0 += kChunk) {
-            float sw[kChunk], sm[kChunk], sv[kChunk];
 #pragma unroll
-            for (int kk = 0; kk < kChunk; ++kk) {
-                const int p = tid + 256 * (k0 + kk);
-                if (p < kNParams) {
-                    sw[kk] = state[p];
-                    sm[kk] = adam_m[p];
-                    sv[kk] = adam_v[p];
-                }
-            }
-#pragma unroll
-            for (int kk = 0; kk < kChunk; ++kk) {
-                const int p = tid + 256 * (k0 + kk);
-                if (p >= kNParams) continue;
-                const float g = ((red[p] + gw[p]) + gw[kNParams + p]) + gw[2 * kNParams + p];
-                if (f.debug_grad && step == 1) f.debug_grad[(size_t)tile * kNParams + p] = g;
-                float w = sw[kk], m = sm[kk], v = sv[kk];
-                m = 0.9f * m + 0.1f * g;
-                v = 0.999f * v + 0.001f * g * g;
-                w -= lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
-                state[p] = w;
-                adam_m[p] = m;
-                adam_v[p] = v;
-                const uint16_t b = to_bf16(w);
-                Wbf[p] = b;
-                if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+        for (int k = 0; k < kSlots; ++k) {
+            const int p = pid[k];
+            const float g = gr[k];
+            const float m = 0.9f * sm[k] + 0.1f * g;
+            const float v = 0.999f * sv[k] + 0.001f * g * g;
+            const float w = sw[k] - lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
+            if (p < 0) continue;
+            if (f.debug_grad && step == 1) f.debug_grad[(size_t)tile * kNParams + p] = g;
+            mw[p] = w;
+            am[p] = m;
+            av[p] = v;
+            const uint16_t b = to_bf16(w);
+            Wbf[p] = b;
+            if (k < 8) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+            if (k >= 12) {
                 if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
                 if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
                 if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // the fitted network: bfloat16 weights and FP32 biases (biases kept at full precision)
     uint16_t *wout = tile_w(f, tile);
     float *bout = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(wout) + kTileBiasOff);
-    for (int p = tid; p < kNParams; p += 256) wout[p] = Wbf[p];
-    for (int p = tid; p < 130; p += 256) bout[p] = sbias[p];
+    for (int p = tid; p < kNParams; p += kTrainThreads) wout[p] = Wbf[p];
+    for (int p = tid; p < 130; p += kTrainThreads) bout[p] = sbias[p];
 }
 
 // ---------------------------------------------------------------- eval: cell grid
@@ -998,7 +1074,7 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_train, dim3(nt), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_mlp_train, dim3(nt), dim3(kTrainThreads), 0, s, f);
     return hipGetLastError();
 }
 

@@ -404,8 +404,8 @@ int validate_ff(const rs_job *job, const rs_ff_config *c, FarGeom &g, bool eval 
     if (!(c->r_near > 0.0) || !std::isfinite(c->r_near)) return fail(RS_EINVAL, "r_near must be finite and > 0");
     if (c->n_samples <= 0 || c->n_samples % 1024) return fail(RS_EINVAL, "n_samples must be a positive multiple of 1024");
     if (c->steps < 0) return fail(RS_EINVAL, "steps < 0");
-    if (c->batch <= 0 || c->batch % 128 || c->n_samples % c->batch)
-        return fail(RS_EINVAL, "batch must be a multiple of 128 dividing n_samples");
+    if (c->batch <= 0 || c->batch % 256 || c->n_samples % c->batch)
+        return fail(RS_EINVAL, "batch must be a multiple of 256 dividing n_samples");
     if (!(c->lr >= 0.0f) || !std::isfinite(c->lr)) return fail(RS_EINVAL, "lr must be finite and >= 0");
     if (!(c->cell_size >= 0.0) || !std::isfinite(c->cell_size)) return fail(RS_EINVAL, "cell_size must be >= 0");
     if (c->shared_x != 0 && c->shared_x != 1) return fail(RS_EINVAL, "shared_x must be 0 or 1");
@@ -485,7 +485,7 @@ rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
 size_t fit_ws_bytes(const FarGeom &g, const rs_ff_config *c)
 {
     return align256((size_t)g.n_tiles * c->n_samples * 2 * sizeof(float)) +
-           align256((size_t)g.n_tiles * rs::kNParams * sizeof(float)) + 256;
+           align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)) + 256;
 }
 
 // Cell grid around the ray window grown by r_near (plus one cell): only lenses there can be near.

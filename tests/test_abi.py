@@ -294,7 +294,8 @@ def test_farfield_validation_without_device():
     assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(good)) > 256
     assert L.rs_farfield_fit_workspace_bytes(ctypes.byref(j), ctypes.byref(good)) > 0
     assert L.rs_farfield_eval_workspace_bytes(ctypes.byref(j), ctypes.byref(good)) > 0
-    for bad in [dict(n_samples=1000), dict(batch=100), dict(batch=384), dict(steps=-1), dict(r_near=0.0),
+    for bad in [dict(n_samples=1000), dict(batch=100), dict(batch=384), dict(batch=128), dict(steps=-1),
+                dict(r_near=0.0),
                 dict(r_near=float("nan")), dict(lr=float("inf")), dict(cell_size=-1.0)]:
         c = _ffcfg(**bad)
         assert L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c)) == 0, bad

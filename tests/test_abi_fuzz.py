@@ -144,7 +144,7 @@ def test_farfield_config_validation_never_crashes(tx, ty, r_near, ns, steps, bat
     c.samples, c.init_params = 0x5000, 0x6000
     nb = L.rs_farfield_model_bytes(ctypes.byref(j), ctypes.byref(c))
     valid = (tx > 0 and ty > 0 and math.isfinite(r_near) and r_near > 0 and ns > 0 and ns % 1024 == 0
-             and steps >= 0 and batch > 0 and batch % 128 == 0 and ns % batch == 0 and math.isfinite(c.lr)
+             and steps >= 0 and batch > 0 and batch % 256 == 0 and ns % batch == 0 and math.isfinite(c.lr)
              and c.lr >= 0 and math.isfinite(cell) and cell >= 0 and shared in (0, 1))
     assert (nb > 0) == valid
     o = _abi.Opts()

@@ -52,8 +52,8 @@ def parse():
                     help="default workload: skip the light-curve, batched and learned far-field measurements")
     ap.add_argument("--legs", default="light_curves,zoom,frames,batched,farfield,large",
                     help="default workload: comma-separated extra measurements to run after the plain one")
-    ap.add_argument("--cpu-seconds", type=float, default=25.0,
-                    help="target wall time of the oracle sample on the host threads (at most 2^22 rays)")
+    ap.add_argument("--cpu-rays", type=int, default=1 << 22,
+                    help="rays of the CPU oracle sample (timed baseline and counted parity)")
     ap.add_argument("--microbench", action="store_true",
                     help="only run the issue-rate probes and print the direct sum's instruction-mix ceiling")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -142,21 +142,16 @@ def workload(name):
     return synth.workload_paper()
 
 
-def cpu_baseline(w, target_wall_s: float, gpu_pix=None):
-    """The FP64 oracle on a bounded sample of the same workload (rays drawn with the counter hash),
-    timed on the host threads; with the GPU's per-ray pixels of the whole grid (gpu_pix) the same
-    sample also gives the counted pixel-switch fraction of the benchmark's own launch."""
+def cpu_baseline(w, n_rays: int, gpu_pix=None):
+    """The FP64 oracle on a bounded sample of the same workload (n_rays rays drawn with the counter
+    hash: by default the 2^22 of the paper-scale parity test, about 30 s on 16 host threads), timed
+    on the host threads; with the GPU's per-ray pixels of the whole grid (gpu_pix) the same sample
+    gives the counted pixel-switch fraction of the benchmark's own launch."""
+    import math
     import oracle
     import synth
     threads = max(1, min(16, os.cpu_count() or 1))
-    # calibrate on a small sample, then size the real one to ~target_wall_s on `threads` threads,
-    # at most 2^22 rays (the parity sample of the paper-scale test)
-    probe = synth.sample_indices(99, w.n_rays, 2048)
-    t0 = time.perf_counter()
-    oracle.trace_parallel(w, probe, threads=threads)
-    per_ray = max(1e-9, (time.perf_counter() - t0) / len(probe))
-    n = int(min(w.n_rays, 1 << 22, max(threads, target_wall_s / per_ray)))
-    idx = synth.sample_indices(12, w.n_rays, n)
+    idx = synth.sample_indices(12, w.n_rays, max(1, min(w.n_rays, n_rays)))
     t0 = time.perf_counter()
     _, p_o = oracle.trace_parallel(w, idx, threads=threads)
     dt = time.perf_counter() - t0
@@ -169,8 +164,10 @@ def cpu_baseline(w, target_wall_s: float, gpu_pix=None):
         g = gpu_pix[idx].astype(np.int64)
         diff = int(np.sum(g != p_o))
         inmap = int(np.sum((g >= 0) | (p_o >= 0)))
+        # a true fraction of at most 1e-5 gives a Poisson count of mean <= 1e-5 n: 3 sigma allowed
         parity = {"rays_checked": int(len(idx)), "rays_in_map": inmap, "rays_switched": diff,
                   "switch_fraction": diff / max(1, inmap), "bar": 1e-5,
+                  "switches_allowed": 1e-5 * inmap + 3.0 * math.sqrt(1e-5 * inmap),
                   "reference": "FP64 oracle, same rays, pixel or lost outcome per ray"}
     return base, parity
 
@@ -697,7 +694,7 @@ def main():
         torch.cuda.synchronize()
         pix = rp.cpu().numpy()
         del ry, rp
-        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_seconds, pix)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_rays, pix)
     print(json.dumps(out), flush=True)
 
 

@@ -104,6 +104,26 @@ def test_affine_base_and_far_samples_match_oracle():
         assert abs(hdr[t, 9] / st - 1) < 2e-3
 
 
+def gradient_term_sums(p, u, t):
+    """Per parameter, the sum over samples of the absolute products that make up its gradient
+    (bfloat16 operands as the bf16 oracle rounds them): |dz1|^T |phi|, |dz2|^T |h1|, |d3|^T |h2| and
+    the sums of |dz1|, |dz2|, |d3| for the biases."""
+    q = mlp.bf16
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(p)
+    o, (phi, z1, h1, z2, h2) = mlp.forward(p, u, bf=True)
+    d3 = (o - t) / len(o)
+    dz2 = q((d3 @ q(W3)) * mlp.silu_grad(z2))
+    dz1 = q((dz2 @ q(W2)) * mlp.silu_grad(z1))
+    out = np.zeros(mlp.N_PARAMS)
+    out[mlp.OFF_W1:mlp.OFF_B1] = (np.abs(dz1).T @ np.abs(phi)).ravel()
+    out[mlp.OFF_B1:mlp.OFF_W2] = np.abs(dz1).sum(0)
+    out[mlp.OFF_W2:mlp.OFF_B2] = (np.abs(dz2).T @ np.abs(h1)).ravel()
+    out[mlp.OFF_B2:mlp.OFF_W3] = np.abs(dz2).sum(0)
+    out[mlp.OFF_W3:mlp.OFF_B3] = (np.abs(d3).T @ np.abs(h2)).ravel()
+    out[mlp.OFF_B3:] = np.abs(d3).sum(0)
+    return out
+
+
 def test_first_step_gradient_matches_bf16_oracle():
     torch, P = _env()
     w = _small_field()
@@ -116,6 +136,13 @@ def test_first_step_gradient_matches_bf16_oracle():
         assert rel < 2e-3, (t, rel)
         for lo_, hi_ in [(mlp.OFF_W1, mlp.OFF_B1), (mlp.OFF_W2, mlp.OFF_B2), (mlp.OFF_W3, mlp.N_PARAMS)]:
             assert np.allclose(g_gpu[t][lo_:hi_], g[lo_:hi_], rtol=0, atol=5e-3 * np.abs(g[lo_:hi_]).max())
+        # every entry: a gradient entry is a sum over the batch of products of bfloat16 values; the
+        # kernel and the oracle differ where a rounding falls the other way (one ulp, 2^-7, per
+        # factor) and in the float32 sums, so |error| <= 2^-6 sum_s |a_s b_s| + 2^-14 of that sum
+        bnd = gradient_term_sums(p0.astype(np.float64), u[:512].astype(np.float64), res[:512] / st)
+        ratio = np.abs(g_gpu[t] - g) / (2.0 ** -6 * bnd + 1e-12)
+        print(f"tile {t}: first-step gradient relative L2 {rel:.1e}, max |err| / per-entry bound {ratio.max():.3f}")
+        assert np.all(ratio <= 1.0), float(ratio.max())
 
 
 def test_training_steps_match_bf16_oracle():

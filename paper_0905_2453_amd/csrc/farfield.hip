@@ -450,13 +450,20 @@ __global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
 // last round the partial sums are exchanged through LDS in a fixed order and each parameter is
 // updated by the lane that owns its gradient: FP32 master weights and Adam moments live in the fit
 // workspace (64.5 KB per tile, read and written once per step: the working set of the tiles in
-// flight stays in L2), the bfloat16 weight copies the MFMAs read and the FP32 biases in LDS.
+// flight stays in L2; one 12-byte record per parameter), the bfloat16 weight copies the MFMAs read
+// and the FP32 biases in LDS.
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Optimiser state of one parameter: FP32 master weight and the two Adam moments, read and written
+// as one 12-byte record.
+struct AdamState {
+    float w, m, v;
+};
 
 constexpr int kTrainWaves = 8;
 constexpr int kTrainThreads = 64 * kTrainWaves;
@@ -476,16 +483,13 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
     const int l16 = lane & 15, l4 = lane >> 4;
-    float *mw = f.state + (size_t)tile * 3 * kNParams;   // FP32 master weights, Adam m, Adam v
-    float *am = mw + kNParams, *av = am + kNParams;
+    AdamState *ost = reinterpret_cast<AdamState *>(f.state) + (size_t)tile * kNParams;
     const float *tgt = f.targets + (size_t)tile * f.n_samples * 2;
     auto stg = [&](int a, int v) { return sstage + (a * kTrainWaves + v) * kStageWords; };
 
     for (int p = tid; p < kNParams; p += kTrainThreads) {
         const float w = f.init_params[p];
-        mw[p] = w;
-        am[p] = 0.f;
-        av[p] = 0.f;
+        ost[p] = AdamState{w, 0.f, 0.f};
         const uint16_t b = to_bf16(w);
         Wbf[p] = b;
         if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
@@ -677,14 +681,9 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
         }
         // the optimiser state of every slot is requested before the partial sums are exchanged, so
         // its global round trip overlaps the exchange
-        float sw[kSlots], sm[kSlots], sv[kSlots];
+        AdamState st[kSlots];
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const uint32_t p = pid[k] < 0 ? 0u : (uint32_t)pid[k];
-            sw[k] = mw[p];
-            sm[k] = am[p];
-            sv[k] = av[p];
-        }
+        for (int k = 0; k < kSlots; ++k) st[k] = ost[pid[k] < 0 ? 0u : (uint32_t)pid[k]];
         __syncthreads();   // the last round's readers are done: the staging area takes the partial sums
         float *xb = reinterpret_cast<float *>(sstage);      // [wave][4][64]: gb1, gb2, gw30, gw31
         float *x3 = xb + kTrainWaves * 4 * 64;               // [wave][2]: gb3
@@ -732,14 +731,12 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
         for (int k = 0; k < kSlots; ++k) {
             const int p = pid[k];
             const float g = gr[k];
-            const float m = 0.9f * sm[k] + 0.1f * g;
-            const float v = 0.999f * sv[k] + 0.001f * g * g;
-            const float w = sw[k] - lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
+            const float m = 0.9f * st[k].m + 0.1f * g;
+            const float v = 0.999f * st[k].v + 0.001f * g * g;
+            const float w = st[k].w - lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
             if (p < 0) continue;
             if (f.debug_grad && step == 1) f.debug_grad[(size_t)tile * kNParams + p] = g;
-            mw[p] = w;
-            am[p] = m;
-            av[p] = v;
+            ost[p] = AdamState{w, m, v};
             const uint16_t b = to_bf16(w);
             Wbf[p] = b;
             if (k < 8) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;

@@ -114,7 +114,7 @@ struct FarArgs {
     const float *samples;         // n_samples x 2 tile-local points in [-1, 1]^2
     const float *init_params;     // kNParams
     float *targets;               // n_tiles x n_samples x 2 (workspace)
-    float *state;                 // n_tiles x 3 kNParams: FP32 master weights, Adam m, Adam v (workspace)
+    float *state;                 // n_tiles x kNParams x (FP32 master weight, Adam m, Adam v) (workspace)
     int32_t n_samples, steps, batch;
     int32_t grid_samples;         // samples 64 (4 g + k) + i, k = 0..3, share their first coordinate
     float lr;

@@ -146,13 +146,34 @@ __device__ __forceinline__ u16x8 w3_row8(const uint16_t *Wbf, int o, int g, int 
     return *reinterpret_cast<const u16x8 *>(Wbf + kOffW3 + 64 * o + 16 * g + 8 * hf);
 }
 
+// The 16 biases of output tile T of a hidden layer, for a lane of half hf, in slot order: units
+// 32 T + 8 hf + e and 32 T + 16 + 8 hf + e (e < 8), four 16-byte LDS reads.
+__device__ __forceinline__ void load_bias16(const float *bias, int T, int hf, float *b)
+{
+    const f32x4 *p0 = reinterpret_cast<const f32x4 *>(bias + 32 * T + 8 * hf);
+    const f32x4 *p1 = reinterpret_cast<const f32x4 *>(bias + 32 * T + 16 + 8 * hf);
+    const f32x4 v0 = p0[0], v1 = p0[1], v2 = p1[0], v3 = p1[1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        b[e] = v0[e];
+        b[4 + e] = v1[e];
+        b[8 + e] = v2[e];
+        b[12 + e] = v3[e];
+    }
+}
+
+// LDS operands are requested before the MFMAs that need them and the activations of the previous
+// tile; a scheduling barrier keeps the compiler from sinking the reads next to their use, where
+// each would expose its full LDS latency.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 template <bool TRAIN>
-__device__ __forceinline__ void activate16(const f32x16 &acc, const float *bias, int T, int hf, float *d, uint32_t *h)
+__device__ __forceinline__ void activate16(const f32x16 &acc, const float *bv, int T, float *d, uint32_t *h)
 {
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
-        const float za = acc[q] + bias[slot_unit(16 * T + q, hf)];
-        const float zb = acc[q + 1] + bias[slot_unit(16 * T + q + 1, hf)];
+        const float za = acc[q] + bv[q];
+        const float zb = acc[q + 1] + bv[q + 1];
         const float sa = sigm(za), sb = sigm(zb);
         const float ha = za * sa, hb = zb * sb;
         if (TRAIN) {
@@ -163,31 +184,59 @@ __device__ __forceinline__ void activate16(const f32x16 &acc, const float *bias,
     }
 }
 
+// Layer 1 (16 features -> 64 units) and layer 2 (64 -> 64) of 32 samples: MFMA, bias, SiLU, with
+// the SiLU derivatives when TRAIN.  Each tile's operands and biases are read from LDS before its
+// MFMAs are issued.
+template <bool TRAIN>
+__device__ __forceinline__ void layer1(const uint16_t *Wbf, const float *sbias, const bf16x8 &bphi, int col, int hf,
+                                       float *d1, uint32_t *h1)
+{
+    bf16x8 a[2];
+    float bv[2][16];
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        a[T] = lds8(Wbf + kOffW1 + perm_row(32 * T + col) * 16 + 8 * hf);
+        load_bias16(sbias, T, hf, bv[T]);
+    }
+    sched_fence();
+    f32x16 acc[2];
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        acc[T] = f32x16{};
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[T], bphi, acc[T], 0, 0, 0);
+    }
+#pragma unroll
+    for (int T = 0; T < 2; ++T) activate16<TRAIN>(acc[T], bv[T], T, d1, h1);
+}
+
+template <bool TRAIN>
+__device__ __forceinline__ void layer2(const uint16_t *Wbf, const float *sbias, const uint32_t *h1, int col, int hf,
+                                       float *d2, uint32_t *h2)
+{
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        bf16x8 a[4];
+        float bv[16];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(Wbf + kOffW2 + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
+        load_bias16(sbias + 64, T, hf, bv);
+        sched_fence();
+        f32x16 acc = {};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk], pack4(h1 + 4 * kk), acc, 0, 0, 0);
+        activate16<TRAIN>(acc, bv, T, d2, h2);
+    }
+}
+
 template <bool TRAIN>
 __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint32_t *phi4, int lane,
                                           Fwd &r)
 {
     const int hf = lane >> 5, col = lane & 31;
     const bf16x8 bphi = pack4(phi4);
-#pragma unroll
-    for (int T = 0; T < 2; ++T) {
-        const int R = 32 * T + col;
-        const bf16x8 a = lds8(Wbf + kOffW1 + perm_row(R) * 16 + 8 * hf);
-        f32x16 acc = {};
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bphi, acc, 0, 0, 0);
-        activate16<TRAIN>(acc, sbias, T, hf, r.d1, r.h1);
-    }
-#pragma unroll
-    for (int T = 0; T < 2; ++T) {
-        const int R = 32 * T + col;
-        f32x16 acc = {};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const bf16x8 a = lds8(Wbf + kOffW2 + perm_row(R) * 64 + 16 * kk + 8 * hf);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(r.h1 + 4 * kk), acc, 0, 0, 0);
-        }
-        activate16<TRAIN>(acc, sbias + 64, T, hf, r.d2, r.h2);
-    }
+    layer1<TRAIN>(Wbf, sbias, bphi, col, hf, r.d1, r.h1);
+    layer2<TRAIN>(Wbf, sbias, r.h1, col, hf, r.d2, r.h2);
     // layer 3 on the VALU: slots 8 g .. 8 g + 7 are the consecutive units 16 g + 8 hf + e
     float po0 = 0.f, po1 = 0.f;
 #pragma unroll
@@ -474,7 +523,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
 {
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
-    __shared__ float sbias[130];
+    __shared__ __attribute__((aligned(16))) float sbias[130];
     // array a (0 dz2, 1 h1, 2 dz1, 3 h2) of wave v at sstage + (a kTrainWaves + v) kStageWords
     __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * kTrainWaves * kStageWords];
     __shared__ __attribute__((aligned(16))) uint16_t sphi[kTrainWaves][16 * 32];
@@ -529,23 +578,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             float d1[32], d2[32];
             uint32_t h1[16], h2[16];
             const bf16x8 bphi = pack4(phi4);
-#pragma unroll
-            for (int T = 0; T < 2; ++T) {
-                const bf16x8 a = lds8(Wbf + kOffW1 + perm_row(32 * T + col) * 16 + 8 * hf);
-                f32x16 acc = {};
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bphi, acc, 0, 0, 0);
-                activate16<true>(acc, sbias, T, hf, d1, h1);
-            }
-#pragma unroll
-            for (int T = 0; T < 2; ++T) {
-                f32x16 acc = {};
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const bf16x8 a = lds8(Wbf + kOffW2 + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(h1 + 4 * kk), acc, 0, 0, 0);
-                }
-                activate16<true>(acc, sbias + 64, T, hf, d2, h2);
-            }
+            layer1<true>(Wbf, sbias, bphi, col, hf, d1, h1);
+            layer2<true>(Wbf, sbias, h1, col, hf, d2, h2);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
@@ -591,12 +625,14 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             uint32_t dz1[16];
 #pragma unroll
             for (int T = 0; T < 2; ++T) {
+                bf16x8 a[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(W2T + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
+                sched_fence();
                 f32x16 acc = {};
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const bf16x8 a = lds8(W2T + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, pack4(dz2 + 4 * kk), acc, 0, 0, 0);
-                }
+                for (int kk = 0; kk < 4; ++kk)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk], pack4(dz2 + 4 * kk), acc, 0, 0, 0);
 #pragma unroll
                 for (int q = 0; q < 16; q += 2)
                     dz1[(16 * T + q) / 2] = pk2(acc[q] * d1[16 * T + q], acc[q + 1] * d1[16 * T + q + 1]);
@@ -840,7 +876,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
 {
     constexpr int CAP = 2048, T = 16;
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
-    __shared__ float sbias[130];
+    __shared__ __attribute__((aligned(16))) float sbias[130];
     __shared__ float4 s_near[CAP];
     __shared__ int s_cells[4];
     __shared__ uint32_t s_lost;

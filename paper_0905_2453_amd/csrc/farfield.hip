@@ -65,6 +65,17 @@ __device__ __forceinline__ int perm_row(int R)
     const int T = R >> 5, rr = R & 31, a = rr >> 3, hf = (rr >> 2) & 1, b = rr & 3;
     return 32 * T + 16 * (a >> 1) + 8 * hf + 4 * (a & 1) + b;
 }
+// The 64 x 64 bfloat16 matrices in LDS (W2, and its transpose in training) keep the 16-byte chunk c of
+// row r at position c ^ wsw(r): the eight rows that one MFMA operand load reads together (rows
+// 8 h + b of a 32-row tile, h < 2, b < 4) then fall on eight different bank groups, and so do the
+// column writes of the optimiser update.
+__device__ __forceinline__ int wsw(int r) { return (r & 3) | (((r >> 3) & 1) << 2); }
+__device__ __forceinline__ int m64(int r, int c) { return r * 64 + ((((c >> 3) ^ wsw(r)) << 3) | (c & 7)); }
+// LDS position of parameter p in the flat bfloat16 weight array (W2 swizzled as above)
+__device__ __forceinline__ int wslot(int p)
+{
+    return (p >= kOffW2 && p < kOffB2) ? kOffW2 + m64((p - kOffW2) >> 6, (p - kOffW2) & 63) : p;
+}
 // logical hidden unit held in slot q (0..31) by a lane of half hf
 __device__ __forceinline__ int slot_unit(int q, int hf) { return 16 * (q >> 3) + 8 * hf + (q & 7); }
 
@@ -140,10 +151,30 @@ struct Fwd {
     float o[2];
 };
 
-// Eight consecutive hidden units' layer-3 weights of output row o (16-byte LDS read).
-__device__ __forceinline__ u16x8 w3_row8(const uint16_t *Wbf, int o, int g, int hf)
+// a . b + c over the two bfloat16 halves of a and b, FP32 sum (v_dot2c_f32_bf16)
+__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
 {
-    return *reinterpret_cast<const u16x8 *>(Wbf + kOffW3 + 64 * o + 16 * g + 8 * hf);
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
+}
+
+// Layer 3 (64 units -> 2) over the lane's 32 units of its sample: word j of h2 holds slots 2j, 2j + 1,
+// the consecutive units 16 g + 8 hf + e, e + 1 (j = 4 g + e / 2), which pair with the consecutive
+// bfloat16 weights of W3's rows.  Two partial sums per output (even and odd g).
+__device__ __forceinline__ void layer3(const uint16_t *Wbf, const uint32_t *h2, int hf, float &po0, float &po1)
+{
+    float a[2][2] = {};
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const u32x4 w0 = *reinterpret_cast<const u32x4 *>(Wbf + kOffW3 + 16 * g + 8 * hf);
+        const u32x4 w1 = *reinterpret_cast<const u32x4 *>(Wbf + kOffW3 + 64 + 16 * g + 8 * hf);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[g & 1][0] = dot2bf(h2[4 * g + j], w0[j], a[g & 1][0]);
+            a[g & 1][1] = dot2bf(h2[4 * g + j], w1[j], a[g & 1][1]);
+        }
+    }
+    po0 = a[0][0] + a[1][0];
+    po1 = a[0][1] + a[1][1];
 }
 
 // The 16 biases of output tile T of a hidden layer, for a lane of half hf, in slot order: units
@@ -218,7 +249,7 @@ __device__ __forceinline__ void layer2(const uint16_t *Wbf, const float *sbias, 
         bf16x8 a[4];
         float bv[16];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(Wbf + kOffW2 + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
+        for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(Wbf + kOffW2 + m64(perm_row(32 * T + col), 16 * kk + 8 * hf));
         load_bias16(sbias + 64, T, hf, bv);
         sched_fence();
         f32x16 acc = {};
@@ -237,19 +268,8 @@ __device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbia
     const bf16x8 bphi = pack4(phi4);
     layer1<TRAIN>(Wbf, sbias, bphi, col, hf, r.d1, r.h1);
     layer2<TRAIN>(Wbf, sbias, r.h1, col, hf, r.d2, r.h2);
-    // layer 3 on the VALU: slots 8 g .. 8 g + 7 are the consecutive units 16 g + 8 hf + e
-    float po0 = 0.f, po1 = 0.f;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t p = r.h2[4 * g + e / 2];
-            const float h = (e & 1) ? hi_bf16(p) : lo_bf16(p);
-            po0 = fmaf(from_bf16(w0[e]), h, po0);
-            po1 = fmaf(from_bf16(w1[e]), h, po1);
-        }
-    }
+    float po0, po1;
+    layer3(Wbf, r.h2, hf, po0, po1);
     // the two halves of a sample live in lanes l and l ^ 32; add them in a fixed order
     const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
     r.o[0] = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
@@ -491,12 +511,14 @@ __global__ void __launch_bounds__(256) k_ff_normalize(const FarArgs f)
 // latencies hide behind the other's work) trains one tile's network with mini-batch Adam.  A step
 // takes its batch in rounds of 256 samples, 32 per wave.  In a round every wave runs the forward
 // and backward pass of its own samples (a lane pair per sample, as in the evaluation) and stages
-// [unit][sample] bfloat16 copies of dz2, h1, dz1 and h2 and the features in LDS; after a
-// workgroup barrier each wave contracts the blocks of the weight gradients it owns over all 256
-// samples (16x16x32 MFMAs): the dW2 blocks of rows 16 (w / 2) .. + 16 and columns 32 (w % 2) .. + 32,
-// and the dW1 rows 16 (w % 4) .. + 16 over the samples of waves 4 (w / 4) .. + 3.  Bias and
-// layer-3 gradients are summed by each wave over its own samples (lane = hidden unit).  After the
-// last round the partial sums are exchanged through LDS in a fixed order and each parameter is
+// sample-major bfloat16 copies of h1, h2, dz2, dz1 and the features in LDS; after a workgroup
+// barrier each wave contracts the blocks of the weight gradients it owns over all 256 samples
+// (16x16x32 MFMAs whose operands come back through transposing LDS reads): the dW2 blocks of rows
+// 16 (w / 2) .. + 16 and columns 32 (w % 2) .. + 32, and the dW1 rows 16 (w % 4) .. + 16 over the
+// samples of waves 4 (w / 4) .. + 3.  The b2 and b1 gradients are the same contractions against a
+// vector of ones (b2 split between the two waves of a row block, half of the samples each); the
+// layer-3 gradients are summed by each wave over its own samples on the VALU, b3's per lane.  After
+// the last round the partial sums are exchanged through LDS in a fixed order and each parameter is
 // updated by the lane that owns its gradient: FP32 master weights and Adam moments live in the fit
 // workspace (64.5 KB per tile, read and written once per step: the working set of the tiles in
 // flight stays in L2; one 12-byte record per parameter), the bfloat16 weight copies the MFMAs read
@@ -508,30 +530,112 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sample-major staging.  Row r (one sample) of a hidden-unit array holds the 64 units as eight
+// 16-byte chunks of eight consecutive units, chunk c stored at position c ^ swz(r); a lane writes its
+// 32 units (slots 8 g .. 8 g + 7 are the units 16 g + 8 hf + e, chunk 2 g + hf) as four chunks.  The
+// swizzle puts the chunks of eight consecutive rows (one write instruction's first lanes) and the
+// two chunks of four consecutive rows (one transposing read's group) on distinct banks.
+__device__ __forceinline__ int swz(int r) { return ((r & 3) << 1) | ((r >> 2) & 1); }
+
+__device__ __forceinline__ void stage_row(uint16_t *arr, int col, int hf, const uint32_t *w)
+{
+    uint8_t *row = reinterpret_cast<uint8_t *>(arr) + col * 128;
+    const int sw = swz(col);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const u32x4 v = {w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]};
+        *reinterpret_cast<u32x4 *>(row + (((2 * g + hf) ^ sw) << 4)) = v;
+    }
+}
+
+using bf16x4 = __bf16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+
+// ds_read_b64_tr_b16: in each group of 16 lanes, element e of result lane 4 q + c is element c of the
+// four bfloat16 values addressed by lane 4 e + q of the group.
+__device__ __forceinline__ bf16x4 lds_tr4(const uint8_t *p)
+{
+    return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4 *)(p));
+}
+
+// 16x16x32 MFMA operand of a staged hidden-unit array: unit 16 b + lane % 16, samples 8 (lane / 16)
+// + 0 .. 7.  Lane 4 e + q of a group addresses units 16 b + 4 q .. + 3 of sample 8 (lane / 16) + 4 h + e.
+__device__ __forceinline__ bf16x8 tr_units(const uint16_t *arr, int b, int lane)
+{
+    const int G = lane >> 4, s = lane & 15;
+    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr);
+    bf16x4 v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = 8 * G + 4 * h + (s >> 2);
+        v[h] = lds_tr4(base + r * 128 + (((2 * b + ((s & 3) >> 1)) ^ swz(r)) << 4) + ((s & 1) << 3));
+    }
+    return __builtin_shufflevector(v[0], v[1], 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// Feature rows: 16 values (32 bytes) per sample, chunk c (features 8 c .. 8 c + 7) of row r at
+// position c ^ ((r >> 2) & 1).  Operand: feature lane % 16, samples 8 (lane / 16) + 0 .. 7.
+__device__ __forceinline__ void stage_phi(uint16_t *arr, int col, int hf, const uint32_t *phi4)
+{
+    const u32x4 v = {phi4[0], phi4[1], phi4[2], phi4[3]};
+    *reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(arr) + col * 32 + ((hf ^ ((col >> 2) & 1)) << 4)) = v;
+}
+__device__ __forceinline__ bf16x8 tr_phi(const uint16_t *arr, int lane)
+{
+    const int G = lane >> 4, s = lane & 15;
+    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr);
+    bf16x4 v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = 8 * G + 4 * h + (s >> 2);
+        v[h] = lds_tr4(base + r * 32 + ((((s & 3) >> 1) ^ ((r >> 2) & 1)) << 4) + ((s & 1) << 3));
+    }
+    return __builtin_shufflevector(v[0], v[1], 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
 // Optimiser state of one parameter: FP32 master weight and the two Adam moments, read and written
 // as one 12-byte record.
 struct AdamState {
     float w, m, v;
 };
 
+// Per-step factors of the optimiser, in FP64 and rounded once: the cosine-decayed learning rate
+// lr (1 + cos(pi (t - 1) / S)) / 2 and the bias corrections 1 / (1 - beta^t) of step t (1-based).
+__global__ void __launch_bounds__(256) k_adam_schedule(const FarArgs f)
+{
+    for (int t = (int)threadIdx.x + 1; t <= f.steps; t += 256) {
+        f.sched[4 * (t - 1)] = (float)((double)f.lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (t - 1) / f.steps)));
+        f.sched[4 * (t - 1) + 3] = 0.f;
+    }
+    if (threadIdx.x == 0) {
+        double b1t = 1.0, b2t = 1.0;
+        for (int t = 1; t <= f.steps; ++t) {
+            b1t *= 0.9;
+            b2t *= 0.999;
+            f.sched[4 * (t - 1) + 1] = (float)(1.0 / (1.0 - b1t));
+            f.sched[4 * (t - 1) + 2] = (float)(1.0 / (1.0 - b2t));
+        }
+    }
+}
+
 constexpr int kTrainWaves = 8;
 constexpr int kTrainThreads = 64 * kTrainWaves;
 constexpr int kRoundSamples = 32 * kTrainWaves;
-constexpr int kStageWords = 64 * 32;   // one [unit][sample] bfloat16 array of one wave
+constexpr int kStageWords = 64 * 32;   // one [sample][unit] bfloat16 array of one wave
 
 __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
 {
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
     __shared__ __attribute__((aligned(16))) float sbias[130];
+    __shared__ __attribute__((aligned(16))) float sW3[128];   // (W3[0][u], W3[1][u]) of unit u, bfloat16 values
     // array a (0 dz2, 1 h1, 2 dz1, 3 h2) of wave v at sstage + (a kTrainWaves + v) kStageWords
     __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * kTrainWaves * kStageWords];
     __shared__ __attribute__((aligned(16))) uint16_t sphi[kTrainWaves][16 * 32];
-    __shared__ float sd3[kTrainWaves][2 * 32];
+    __shared__ __attribute__((aligned(16))) float sd3[kTrainWaves][2 * 32];
 
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
-    const int l16 = lane & 15, l4 = lane >> 4;
     AdamState *ost = reinterpret_cast<AdamState *>(f.state) + (size_t)tile * kNParams;
     const float *tgt = f.targets + (size_t)tile * f.n_samples * 2;
     auto stg = [&](int a, int v) { return sstage + (a * kTrainWaves + v) * kStageWords; };
@@ -540,66 +644,85 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
         const float w = f.init_params[p];
         ost[p] = AdamState{w, 0.f, 0.f};
         const uint16_t b = to_bf16(w);
-        Wbf[p] = b;
-        if (p >= kOffW2 && p < kOffB2) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
+        Wbf[wslot(p)] = b;
+        if (p >= kOffW2 && p < kOffB2) W2T[m64((p - kOffW2) & 63, (p - kOffW2) >> 6)] = b;
         if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
         if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
+        if (p >= kOffW3 && p < kOffB3) sW3[2 * ((p - kOffW3) & 63) + (p - kOffW3) / 64] = from_bf16(b);
         if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
     }
     // (the first round's barrier orders these stores before their use)
 
     const int rounds = f.batch / kRoundSamples;
     const float inv_b = 1.0f / (float)f.batch;
-    const int jb = wave >> 1, ib0 = 2 * (wave & 1);   // owned dW2 blocks: rows 16 jb, columns 16 ib0 .. + 32
-    const int t4 = wave & 3, vh = 4 * (wave >> 2);     // owned dW1 rows 16 t4, over waves vh .. vh + 3
+    // owned blocks: dW2 rows 32 R .. + 32, columns 32 C .. + 32 (R, C from w % 4) and the dW1 rows
+    // 16 (w % 4) .. + 16, both over the samples of waves 4 (w / 4) .. + 3; b2 of rows 32 R + 16 C .. + 16
     uint16_t *z2s = stg(0, wave), *h1s = stg(1, wave), *z1s = stg(2, wave), *h2s = stg(3, wave);
-    uint16_t *phs = sphi[wave];
     float *d3s = sd3[wave];
-    double b1t = 1.0, b2t = 1.0;
-    for (int step = 1; step <= f.steps; ++step) {
-        const int i0 = (int)(((int64_t)(step - 1) * f.batch) % f.n_samples);
-        f32x4 g2[2] = {}, g1 = {};
-        float gb1 = 0.f, gb2 = 0.f, gw30 = 0.f, gw31 = 0.f, gb3 = 0.f;
-        for (int rd = 0; rd < rounds; ++rd) {
+    const u32x4 ones_u = {0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u};
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, ones_u);
+    // the sample of the next round (samples of step t start at (t - 1) B mod N; B divides N), requested
+    // a round ahead
+    float u_n, t0_n, t1_n;
+    auto fetch = [&](int base) __attribute__((always_inline)) {
+        const int si = base + 32 * wave + col;
+        u_n = f.samples[2 * si + hf];
+        t0_n = tgt[2 * si];
+        t1_n = tgt[2 * si + 1];
+    };
+    fetch(0);
+    for (int step = 1, i0 = 0; step <= f.steps; ++step, i0 = (i0 + f.batch == f.n_samples) ? 0 : i0 + f.batch) {
+        f32x4 g2[2][2] = {}, g1 = {}, gb1v = {}, gb2v = {};
+        float w3a[8] = {};            // dW3 [block b][output o]: unit 16 b + lane % 16, samples 8 (lane / 16) ..
+        float gb3a0 = 0.f, gb3a1 = 0.f;
+        // owned weight-gradient blocks contracted over this round's samples, in wave order (the
+        // operand addresses are recomputed here from laundered indices, not kept across the round)
+        auto contract = [&]() __attribute__((always_inline)) {
+            int cl = lane, cw = wave;
+            asm volatile("" : "+v"(cl), "+v"(cw));
+            const int r2 = (cw & 3) >> 1, c2 = cw & 1, tt = cw & 3, vv = 4 * (cw >> 2);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                bf16x8 a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[i] = tr_units(stg(0, vv + v), 2 * r2 + i, cl);
+                    b[i] = tr_units(stg(1, vv + v), 2 * c2 + i, cl);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        g2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], g2[i][j], 0, 0, 0);
+                gb2v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c2 ? a[1] : a[0], ones, gb2v, 0, 0, 0);
+                const bf16x8 a1 = tr_units(stg(2, vv + v), tt, cl);
+                const bf16x8 b1 = tr_phi(sphi[vv + v], cl);
+                g1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, g1, 0, 0, 0);
+                gb1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, ones, gb1v, 0, 0, 0);
+            }
+        };
+        for (int rd = 0;; ++rd) {
             // the staging area's readers of the previous round (or the last update's parameter
             // copies) are done
             __syncthreads();
-            const int si = i0 + kRoundSamples * rd + 32 * wave + col;
-            const float u = f.samples[2 * si + hf];
-            const float t0 = tgt[2 * si], t1 = tgt[2 * si + 1];
+            const float u = u_n, t0 = t0_n, t1 = t1_n;
+            {
+                const int nb = i0 + kRoundSamples * (rd + 1);
+                fetch(nb == f.n_samples ? 0 : nb);
+            }
             uint32_t phi4[4];
             features8(u, phi4);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                phs[(8 * hf + 2 * k) * 32 + col] = (uint16_t)phi4[k];
-                phs[(8 * hf + 2 * k + 1) * 32 + col] = (uint16_t)(phi4[k] >> 16);
-            }
+            stage_phi(sphi[wave], col, hf, phi4);
             // forward: layer 1, layer 2 (each staged as soon as it is computed), layer 3
             float d1[32], d2[32];
             uint32_t h1[16], h2[16];
             const bf16x8 bphi = pack4(phi4);
             layer1<true>(Wbf, sbias, bphi, col, hf, d1, h1);
+            stage_row(h1s, col, hf, h1);
             layer2<true>(Wbf, sbias, h1, col, hf, d2, h2);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
-                h1s[ua * 32 + col] = (uint16_t)h1[j];
-                h1s[ub * 32 + col] = (uint16_t)(h1[j] >> 16);
-                h2s[ua * 32 + col] = (uint16_t)h2[j];
-                h2s[ub * 32 + col] = (uint16_t)(h2[j] >> 16);
-            }
-            float po0 = 0.f, po1 = 0.f;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint32_t pr = h2[4 * g + e / 2];
-                    const float h = (e & 1) ? hi_bf16(pr) : lo_bf16(pr);
-                    po0 = fmaf(from_bf16(w0[e]), h, po0);
-                    po1 = fmaf(from_bf16(w1[e]), h, po1);
-                }
-            }
+            stage_row(h2s, col, hf, h2);
+            float po0, po1;
+            layer3(Wbf, h2, hf, po0, po1);
             const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
             const float o0 = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
             const float o1 = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
@@ -608,26 +731,28 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 d3s[col] = d30;
                 d3s[32 + col] = d31;
             }
-            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3
+            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 (the bfloat16 weights as FP32 pairs)
             uint32_t dz2[16];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const u16x8 w0 = w3_row8(Wbf, 0, g, hf), w1 = w3_row8(Wbf, 1, g, hf);
+                const f32x4 *wp = reinterpret_cast<const f32x4 *>(sW3 + 2 * (16 * g + 8 * hf));
 #pragma unroll
                 for (int e = 0; e < 8; e += 2) {
                     const int q = 8 * g + e;
-                    const float dha = fmaf(from_bf16(w0[e]), d30, from_bf16(w1[e]) * d31);
-                    const float dhb = fmaf(from_bf16(w0[e + 1]), d30, from_bf16(w1[e + 1]) * d31);
+                    const f32x4 w = wp[e / 2];
+                    const float dha = fmaf(w[0], d30, w[1] * d31);
+                    const float dhb = fmaf(w[2], d30, w[3] * d31);
                     dz2[q / 2] = pk2(dha * d2[q], dhb * d2[q + 1]);
                 }
             }
+            stage_row(z2s, col, hf, dz2);
             // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
             uint32_t dz1[16];
 #pragma unroll
             for (int T = 0; T < 2; ++T) {
                 bf16x8 a[4];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(W2T + perm_row(32 * T + col) * 64 + 16 * kk + 8 * hf);
+                for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(W2T + m64(perm_row(32 * T + col), 16 * kk + 8 * hf));
                 sched_fence();
                 f32x16 acc = {};
 #pragma unroll
@@ -637,75 +762,60 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 for (int q = 0; q < 16; q += 2)
                     dz1[(16 * T + q) / 2] = pk2(acc[q] * d1[16 * T + q], acc[q + 1] * d1[16 * T + q + 1]);
             }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int ua = slot_unit(2 * j, hf), ub = slot_unit(2 * j + 1, hf);
-                z2s[ua * 32 + col] = (uint16_t)dz2[j];
-                z2s[ub * 32 + col] = (uint16_t)(dz2[j] >> 16);
-                z1s[ua * 32 + col] = (uint16_t)dz1[j];
-                z1s[ub * 32 + col] = (uint16_t)(dz1[j] >> 16);
-            }
+            stage_row(z1s, col, hf, dz1);
             // this wave's own staging: a wave-scope fence orders its stores and loads
             wave_sync();
-            // bias gradients and dW3 over this wave's samples: lane = hidden unit (16-byte loads,
-            // sums in sample order)
+            // dW3 and b3 over this wave's samples: lane = unit 16 b + lane % 16, samples 8 G .. 8 G + 7
             {
-                float s1 = 0.f, s2 = 0.f, w0 = 0.f, w1 = 0.f;
+                int dl = lane, dw = wave;
+                asm volatile("" : "+v"(dl), "+v"(dw));
+                const int G = dl >> 4;
+                const float *d3s = sd3[dw];
+                const uint16_t *h2s = stg(3, dw);
+                const f32x4 da0 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G);
+                const f32x4 da1 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G + 4);
+                const f32x4 db0 = *reinterpret_cast<const f32x4 *>(d3s + 32 + 8 * G);
+                const f32x4 db1 = *reinterpret_cast<const f32x4 *>(d3s + 32 + 8 * G + 4);
 #pragma unroll
-                for (int s8 = 0; s8 < 32; s8 += 8) {
-                    const u16x8 vz2 = *reinterpret_cast<const u16x8 *>(z2s + lane * 32 + s8);
-                    const u16x8 vz1 = *reinterpret_cast<const u16x8 *>(z1s + lane * 32 + s8);
-                    const u16x8 vh2 = *reinterpret_cast<const u16x8 *>(h2s + lane * 32 + s8);
+                for (int e = 0; e < 4; ++e) {
+                    gb3a0 += da0[e];
+                    gb3a1 += db0[e];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    gb3a0 += da1[e];
+                    gb3a1 += db1[e];
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const u16x8 hv = __builtin_bit_cast(u16x8, tr_units(h2s, b, dl));
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        s2 += from_bf16(vz2[e]);
-                        s1 += from_bf16(vz1[e]);
-                        const float h = from_bf16(vh2[e]);
-                        w0 = fmaf(d3s[s8 + e], h, w0);
-                        w1 = fmaf(d3s[32 + s8 + e], h, w1);
+                        const float h = from_bf16(hv[e]);
+                        w3a[2 * b] = fmaf(e < 4 ? da0[e & 3] : da1[e & 3], h, w3a[2 * b]);
+                        w3a[2 * b + 1] = fmaf(e < 4 ? db0[e & 3] : db1[e & 3], h, w3a[2 * b + 1]);
                     }
-                }
-                gb2 += s2;
-                gb1 += s1;
-                gw30 += w0;
-                gw31 += w1;
-                if (lane < 2) {
-                    float s3 = 0.f;
-                    for (int s = 0; s < 32; ++s) s3 += d3s[32 * lane + s];
-                    gb3 += s3;
                 }
             }
             __syncthreads();   // every wave's staging of this round is complete
-            // owned weight-gradient blocks, contracted over the round's samples in wave order
-#pragma unroll
-            for (int v = 0; v < kTrainWaves; ++v) {
-                const bf16x8 a = lds8(stg(0, v) + (16 * jb + l16) * 32 + 8 * l4);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const bf16x8 b = lds8(stg(1, v) + (16 * (ib0 + c) + l16) * 32 + 8 * l4);
-                    g2[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g2[c], 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const bf16x8 a = lds8(stg(2, vh + v) + (16 * t4 + l16) * 32 + 8 * l4);
-                const bf16x8 b = lds8(sphi[vh + v] + l16 * 32 + 8 * l4);
-                g1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1, 0, 0, 0);
-            }
+            if (rd + 1 == rounds) break;
+            contract();
         }
-        // The lane's parameters: slots 0-7 dW2, 8-11 dW1 (waves 0-3), 12-15 the biases and layer-3
-        // weights of unit 8 w + lane (lanes 0-7), slot 12 b3 (wave 0, lanes 8 and 9); -1 = none.
-        // The lane index is passed through an empty asm statement so that these indices are
-        // recomputed here every step (a few integer operations) instead of being kept, or spilled,
-        // across the rounds.
+        // From here to the end of the step the lane and wave indices are passed through an empty asm
+        // statement, so that the addresses and indices derived from them are recomputed every step
+        // (a few integer operations) instead of being kept, or spilled, across the rounds.
         int ln = lane, wv = wave;
         asm volatile("" : "+v"(ln), "+v"(wv));
-        const int m16 = ln & 15, q4 = ln >> 4;
+        // The lane's parameters: slots 0-7 dW2 (tiles (i, w / 4) of its block), 8-11 dW1 (waves 0-3),
+        // 12-15 the biases and layer-3 weights of unit 8 w + lane (lanes 0-7), slot 12 b3 (wave 0,
+        // lanes 8 and 9); -1 = none.
+        const int m16 = ln & 15, q4 = ln >> 4, own = wv >> 2;
         constexpr int kSlots = 16;
         int pid[kSlots];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            pid[k] = kOffW2 + 64 * (16 * (wv >> 1) + 4 * q4 + (k & 3)) + 16 * (2 * (wv & 1) + (k >> 2)) + m16;
+            pid[k] = kOffW2 + 64 * (32 * ((wv & 3) >> 1) + 16 * (k >> 2) + 4 * q4 + (k & 3)) + 32 * (wv & 1) + 16 * own +
+                     m16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) pid[8 + r] = wv < 4 ? kOffW1 + 16 * (16 * (wv & 3) + 4 * q4 + r) + m16 : -1;
         {
@@ -715,79 +825,162 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             pid[14] = ln < 8 ? kOffW3 + un : -1;
             pid[15] = ln < 8 ? kOffW3 + 64 + un : -1;
         }
-        // the optimiser state of every slot is requested before the partial sums are exchanged, so
-        // its global round trip overlaps the exchange
+        // the optimiser state of every slot is requested before the last round's contraction and the
+        // exchange, so its global round trip overlaps them
         AdamState st[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) st[k] = ost[pid[k] < 0 ? 0u : (uint32_t)pid[k]];
-        __syncthreads();   // the last round's readers are done: the staging area takes the partial sums
-        float *xb = reinterpret_cast<float *>(sstage);      // [wave][4][64]: gb1, gb2, gw30, gw31
-        float *x3 = xb + kTrainWaves * 4 * 64;               // [wave][2]: gb3
-        float *x1 = x3 + kTrainWaves * 2;                    // [wave - 4][lane][4]: dW1 partials of waves 4-7
-        xb[(wave * 4 + 0) * 64 + lane] = gb1;
-        xb[(wave * 4 + 1) * 64 + lane] = gb2;
-        xb[(wave * 4 + 2) * 64 + lane] = gw30;
-        xb[(wave * 4 + 3) * 64 + lane] = gw31;
-        if (lane < 2) x3[wave * 2 + lane] = gb3;
-        if (wave >= 4) {
+        contract();
+        // b3 and dW3: the four sample groups of each unit
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x1[((wave - 4) * 64 + lane) * 4 + r] = g1[r];
+        for (int k = 0; k < 8; ++k) {
+            w3a[k] += __shfl_xor(w3a[k], 16);
+            w3a[k] += __shfl_xor(w3a[k], 32);
+        }
+        gb3a0 += __shfl_xor(gb3a0, 16);
+        gb3a0 += __shfl_xor(gb3a0, 32);
+        gb3a1 += __shfl_xor(gb3a1, 16);
+        gb3a1 += __shfl_xor(gb3a1, 32);
+        __syncthreads();   // the last round's readers are done: the staging area takes the partial sums
+        float *xg1 = reinterpret_cast<float *>(sstage);    // [wave / 4][unit]: b1 partials
+        float *xg2 = xg1 + 2 * 64;                         // [wave / 4][unit]: b2 partials
+        float *xw3 = xg2 + 2 * 64;                         // [wave][o][unit]: dW3 partials
+        float *x3 = xw3 + kTrainWaves * 2 * 64;            // [wave][o]: b3 partials
+        float *x1 = x3 + kTrainWaves * 2;                  // [wave - 4][lane][4]: dW1 partials of waves 4-7
+        float *x2 = x1 + 4 * 64 * 4;                       // [wave][lane][8]: dW2 tiles the wave does not own
+        if ((ln & 15) == 0) {
+            *reinterpret_cast<f32x4 *>(xg1 + own * 64 + 16 * (wv & 3) + 4 * (ln >> 4)) = gb1v;
+            *reinterpret_cast<f32x4 *>(xg2 + own * 64 + 32 * ((wv & 3) >> 1) + 16 * (wv & 1) + 4 * (ln >> 4)) = gb2v;
+        }
+        if (ln < 16) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                xw3[(wv * 2 + 0) * 64 + 16 * b + ln] = w3a[2 * b];
+                xw3[(wv * 2 + 1) * 64 + 16 * b + ln] = w3a[2 * b + 1];
+            }
+        }
+        if (ln == 0) {
+            x3[wv * 2] = gb3a0;
+            x3[wv * 2 + 1] = gb3a1;
+        }
+        if (wv >= 4) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x1[((wv - 4) * 64 + ln) * 4 + r] = g1[r];
+        }
+        {
+            // the partner wave (the other sample half of the same block) owns tiles (i, 1 - w / 4)
+            f32x4 *o = reinterpret_cast<f32x4 *>(x2 + (wv * 64 + ln) * 8);
+            o[0] = own ? g2[0][0] : g2[0][1];
+            o[1] = own ? g2[1][0] : g2[1][1];
         }
         __syncthreads();
         float gr[kSlots];
+        {
+            const f32x4 *o = reinterpret_cast<const f32x4 *>(x2 + ((wv ^ 4) * 64 + ln) * 8);
+            const f32x4 p0 = o[0], p1 = o[1];
+            const f32x4 m0 = own ? g2[0][1] : g2[0][0], m1 = own ? g2[1][1] : g2[1][0];
+            // half 0 (waves 0-3) first
 #pragma unroll
-        for (int k = 0; k < 8; ++k) gr[k] = g2[k >> 2][k & 3];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gr[8 + r] = wave < 4 ? g1[r] + x1[(wave * 64 + lane) * 4 + r] : 0.f;
-        if (lane < 8) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float g = 0.f;
-#pragma unroll
-                for (int v = 0; v < kTrainWaves; ++v) g += xb[(v * 4 + k) * 64 + 8 * wave + lane];
-                gr[12 + k] = g;
+            for (int r = 0; r < 4; ++r) {
+                gr[r] = own ? p0[r] + m0[r] : m0[r] + p0[r];
+                gr[4 + r] = own ? p1[r] + m1[r] : m1[r] + p1[r];
             }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gr[8 + r] = wv < 4 ? g1[r] + x1[(wv * 64 + ln) * 4 + r] : 0.f;
+        if (ln < 8) {
+            const int un = 8 * wv + ln;
+            gr[12] = xg1[un] + xg1[64 + un];
+            gr[13] = xg2[un] + xg2[64 + un];
+            float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+            for (int v = 0; v < kTrainWaves; ++v) {
+                s0 += xw3[(v * 2 + 0) * 64 + un];
+                s1 += xw3[(v * 2 + 1) * 64 + un];
+            }
+            gr[14] = s0;
+            gr[15] = s1;
         } else {
             float g = 0.f;
-            if (wave == 0 && lane < 10) {
+            if (wv == 0 && ln < 10) {
 #pragma unroll
-                for (int v = 0; v < kTrainWaves; ++v) g += x3[v * 2 + lane - 8];
+                for (int v = 0; v < kTrainWaves; ++v) g += x3[v * 2 + ln - 8];
             }
             gr[12] = g;
             gr[13] = gr[14] = gr[15] = 0.f;
         }
-        // Adam with bias correction and a cosine-decayed learning rate
-        b1t *= 0.9;
-        b2t *= 0.999;
-        const float lr_t = (float)((double)f.lr * 0.5 * (1.0 + cos(3.14159265358979323846 * (step - 1) / f.steps)));
-        // bias corrections as per-step reciprocals; the per-parameter quotient by the hardware
-        // reciprocal (1 ulp, far below the bfloat16 rounding of the weights)
-        const float ibc1 = (float)(1.0 / (1.0 - b1t)), ibc2 = (float)(1.0 / (1.0 - b2t));
+        // Adam with bias correction and a cosine-decayed learning rate (the step's factors from the
+        // schedule table); square root and quotient by the hardware instructions (1 ulp, far below
+        // the bfloat16 rounding of the weights)
+        const f32x4 sc = *reinterpret_cast<const f32x4 *>(f.sched + 4 * (step - 1));
+        const float lr_t = sc[0], ibc1 = sc[1], ibc2 = sc[2];
+        const bool dbg = f.debug_grad != nullptr && step == 1;
+        float *dg = f.debug_grad + (size_t)tile * kNParams;
+        auto adam = [&](const AdamState &s0, float g) __attribute__((always_inline)) {
+            const float m = 0.9f * s0.m + 0.1f * g;
+            const float v = 0.999f * s0.v + 0.001f * g * g;
+            const float d = __builtin_amdgcn_sqrtf(v * ibc2) + 1e-8f;
+            return AdamState{s0.w - lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(d), m, v};
+        };
+        {
+            // dW2 slots 4 i + r: row 32 R + 16 i + 4 q4 + r, column 32 C + 16 (w / 4) + m16; their LDS
+            // positions in the swizzled W2 and W2T (see m64) follow from that structure
+            const int q4b = q4 & 3, R = (wv & 3) >> 1;
+            const int col2 = 32 * (wv & 1) + 16 * own + m16, rowb = 32 * R + 4 * q4b;
+            const int cx = (col2 >> 3) ^ ((q4b & 2) << 1);
+            const int y = (4 * R + (q4b >> 1)) ^ wsw(col2);
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const int p = pid[k];
-            const float g = gr[k];
-            const float m = 0.9f * st[k].m + 0.1f * g;
-            const float v = 0.999f * st[k].v + 0.001f * g * g;
-            const float w = st[k].w - lr_t * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + 1e-8f);
-            if (p < 0) continue;
-            if (f.debug_grad && step == 1) f.debug_grad[(size_t)tile * kNParams + p] = g;
-            ost[p] = AdamState{w, m, v};
-            const uint16_t b = to_bf16(w);
-            Wbf[p] = b;
-            if (k < 8) W2T[((p - kOffW2) & 63) * 64 + (p - kOffW2) / 64] = b;
-            if (k >= 12) {
-                if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
-                if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
-                if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
+            for (int k = 0; k < 8; ++k) {
+                const int i = k >> 2, r = k & 3;
+                const int row = rowb + 16 * i + r;
+                const int p = kOffW2 + 64 * row + col2;
+                const AdamState s1 = adam(st[k], gr[k]);
+                if (dbg) dg[p] = gr[k];
+                ost[p] = s1;
+                const uint16_t b = to_bf16(s1.w);
+                Wbf[kOffW2 + 64 * row + (((cx ^ r) << 3) | (col2 & 7))] = b;
+                W2T[col2 * 64 + (((y ^ (2 * i)) << 3) | (4 * (q4b & 1) + r))] = b;
             }
+        }
+        if (wv < 4) {
+            // dW1 slots: rows 16 w + 4 q4 + r, feature m16
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = kOffW1 + 16 * (16 * (wv & 3) + 4 * q4 + r) + m16;
+                const AdamState s1 = adam(st[8 + r], gr[8 + r]);
+                if (dbg) dg[p] = gr[8 + r];
+                ost[p] = s1;
+                Wbf[p] = to_bf16(s1.w);
+            }
+        }
+        if (ln < 8) {
+            // b1, b2 and the two layer-3 weights of unit 8 w + lane
+            const int un = 8 * wv + ln;
+            const int ps[4] = {kOffB1 + un, kOffB2 + un, kOffW3 + un, kOffW3 + 64 + un};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const AdamState s1 = adam(st[12 + k], gr[12 + k]);
+                if (dbg) dg[ps[k]] = gr[12 + k];
+                ost[ps[k]] = s1;
+                const uint16_t b = to_bf16(s1.w);
+                Wbf[ps[k]] = b;
+                if (k < 2) sbias[64 * k + un] = s1.w;
+                else sW3[2 * un + k - 2] = from_bf16(b);
+            }
+        } else if (wv == 0 && ln < 10) {
+            const int p = kOffB3 + ln - 8;
+            const AdamState s1 = adam(st[12], gr[12]);
+            if (dbg) dg[p] = gr[12];
+            ost[p] = s1;
+            Wbf[p] = to_bf16(s1.w);
+            sbias[128 + ln - 8] = s1.w;
         }
     }
     __syncthreads();
     // the fitted network: bfloat16 weights and FP32 biases (biases kept at full precision)
     uint16_t *wout = tile_w(f, tile);
     float *bout = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(wout) + kTileBiasOff);
-    for (int p = tid; p < kNParams; p += kTrainThreads) wout[p] = Wbf[p];
+    for (int p = tid; p < kNParams; p += kTrainThreads) wout[p] = Wbf[wslot(p)];
     for (int p = tid; p < 130; p += kTrainThreads) bout[p] = sbias[p];
 }
 
@@ -894,7 +1087,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     const double a01 = ab[0], a02 = ab[1], j11 = ab[2], j12 = ab[3], j22 = ab[4], st = hd[9];
     const uint16_t *wsrc = tile_w(f, tile);
     const float *bsrc = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(wsrc) + kTileBiasOff);
-    for (int p = tid; p < kNParams; p += 256) Wbf[p] = wsrc[p];
+    for (int p = tid; p < kNParams; p += 256) Wbf[wslot(p)] = wsrc[p];
     for (int p = tid; p < 130; p += 256) sbias[p] = bsrc[p];
     if (tid == 0) {
         s_lost = 0u;
@@ -1107,6 +1300,10 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (f.steps > 0) {
+        hipLaunchKernelGGL(k_adam_schedule, dim3(1), dim3(256), 0, s, f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_mlp_train, dim3(nt), dim3(kTrainThreads), 0, s, f);
     return hipGetLastError();
 }

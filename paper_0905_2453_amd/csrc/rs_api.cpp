@@ -485,7 +485,8 @@ rs::FarArgs far_args(const rs_job *job, const rs_ff_config *c, const FarGeom &g)
 size_t fit_ws_bytes(const FarGeom &g, const rs_ff_config *c)
 {
     return align256((size_t)g.n_tiles * c->n_samples * 2 * sizeof(float)) +
-           align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)) + 256;
+           align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)) + align256((size_t)c->steps * 4 * sizeof(float)) +
+           256;
 }
 
 // Cell grid around the ray window grown by r_near (plus one cell): only lenses there can be near.
@@ -864,6 +865,8 @@ int rs_farfield_fit(const rs_job *job, const rs_ff_config *cfg, void *model, siz
     f.model = static_cast<uint8_t *>(model);
     f.targets = reinterpret_cast<float *>(base);
     f.state = reinterpret_cast<float *>(base + align256((size_t)g.n_tiles * cfg->n_samples * 2 * sizeof(float)));
+    f.sched = reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(f.state) +
+                                        align256((size_t)g.n_tiles * 3 * rs::kNParams * sizeof(float)));
     const hipError_t e = rs::launch_ff_fit(f, ff_hash(job, cfg), reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RS_OK : dev_fail(e, "far-field fit launch");
 }

@@ -115,6 +115,7 @@ struct FarArgs {
     const float *init_params;     // kNParams
     float *targets;               // n_tiles x n_samples x 2 (workspace)
     float *state;                 // n_tiles x kNParams x (FP32 master weight, Adam m, Adam v) (workspace)
+    float *sched;                 // steps x 4: learning rate, 1 / (1 - beta1^t), 1 / (1 - beta2^t), 0 (workspace)
     int32_t n_samples, steps, batch;
     int32_t grid_samples;         // samples 64 (4 g + k) + i, k = 0..3, share their first coordinate
     float lr;

@@ -145,6 +145,59 @@ def test_first_step_gradient_matches_bf16_oracle():
         assert np.all(ratio <= 1.0), float(ratio.max())
 
 
+def _assemble(wts, bias):
+    """Flat parameter vector of a tile from the model's bfloat16 weights and FP32 biases."""
+    p = wts.copy()
+    p[mlp.OFF_B1:mlp.OFF_W2] = bias[:64]
+    p[mlp.OFF_B2:mlp.OFF_W3] = bias[64:128]
+    p[mlp.OFF_B3:] = bias[128:130]
+    return p
+
+
+def _bf16_ulp(x):
+    a = np.maximum(np.abs(x), 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(a)) - 7)
+
+
+def test_first_adam_step_per_parameter():
+    # After one bias-corrected Adam step (learning rate lr at step 1) every parameter sits at
+    # w0 - lr g / (|g| + 1e-8).  Checked entry by entry: against the kernel's own gradient (the
+    # update arithmetic: bfloat16 weights within one bfloat16 ulp, FP32 biases within 2^-18 lr), and
+    # against the oracle's gradient wherever the two must agree on its sign (|g| above the
+    # gradient's per-entry error bound); elsewhere the parameter moved by at most lr.
+    torch, P = _env()
+    w = _small_field()
+    job, cfg, model, dg, dt, u, p0, keep = _fit(torch, P, w, WIN, steps=1, debug=True)
+    _, wts, bias = _records(model, 8)
+    g_gpu = dg.cpu().numpy().astype(np.float64)
+    lr = 1e-2
+    is_b = np.zeros(mlp.N_PARAMS, dtype=bool)
+    is_b[mlp.OFF_B1:mlp.OFF_W2] = is_b[mlp.OFF_B2:mlp.OFF_W3] = is_b[mlp.OFF_B3:] = True
+    w0 = p0.astype(np.float64)
+    z = np.zeros(mlp.N_PARAMS)
+    for t in (0, 5):
+        p_g = _assemble(wts[t], bias[t])
+        own = mlp.adam_step(w0, g_gpu[t], z, z, 1, mlp.lr_at(lr, 1, 1))[0]
+        err = np.abs(p_g - own)
+        assert np.all(err[~is_b] <= _bf16_ulp(own[~is_b])), float((err[~is_b] / _bf16_ulp(own[~is_b])).max())
+        assert np.all(err[is_b] <= 2.0 ** -18 * lr), float(err[is_b].max())
+        res, st, *_ = off.tile_targets(w, WIN, TILE, t % 4, t // 4, R_NEAR, u, threads=16)
+        ub, tb = u[:512].astype(np.float64), res[:512] / st
+        g = mlp.gradient(w0, ub, tb, bf=True)
+        bnd = 2.0 ** -6 * gradient_term_sums(w0, ub, tb) + 1e-12
+        ref = mlp.adam_step(w0, g, z, z, 1, mlp.lr_at(lr, 1, 1))[0]
+        sure = np.abs(g) > bnd
+        err = np.abs(p_g - ref)
+        ws, bs = sure & ~is_b, sure & is_b
+        assert np.all(err[ws] <= _bf16_ulp(ref[ws]))
+        assert np.all(err[bs] <= 2.0 ** -18 * lr)
+        # |update| <= lr (a few FP32 ulps over for the biases), plus the bfloat16 rounding of w0 -+ lr
+        moved = np.abs(p_g - w0)[~sure]
+        assert np.all(moved <= lr * (1 + 2.0 ** -20) + 2.0 ** -8 * (np.abs(w0[~sure]) + lr)), float(moved.max() / lr)
+        print(f"tile {t}: first Adam step, {int(sure.sum())} of {mlp.N_PARAMS} entries with a certain sign; "
+              f"max weight error {float((err[ws] / _bf16_ulp(ref[ws])).max()):.2f} bfloat16 ulp")
+
+
 def test_training_steps_match_bf16_oracle():
     torch, P = _env()
     w = _small_field()
@@ -155,10 +208,7 @@ def test_training_steps_match_bf16_oracle():
     res, st, *_ = off.tile_targets(w, WIN, TILE, t % 4, t // 4, R_NEAR, u, threads=16)
     tgt = res / st
     p_o = mlp.train(p0.astype(np.float64), u.astype(np.float64), tgt, steps=steps, batch=512, lr=1e-2, bf=True)
-    p_g = wts[t].copy()
-    p_g[mlp.OFF_B1:mlp.OFF_W2] = bias[t][:64]
-    p_g[mlp.OFF_B2:mlp.OFF_W3] = bias[t][64:128]
-    p_g[mlp.OFF_B3:] = bias[t][128:130]
+    p_g = _assemble(wts[t], bias[t])
     moved = np.linalg.norm(p_o - p0)
     assert np.linalg.norm(p_g - p_o) / moved < 0.05
     l0 = mlp.loss(p0.astype(np.float64), u, tgt, bf=True)

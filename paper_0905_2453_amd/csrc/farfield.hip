@@ -177,13 +177,16 @@ __device__ __forceinline__ void layer3(const uint16_t *Wbf, const uint32_t *h2, 
     po1 = a[0][1] + a[1][1];
 }
 
-// The 16 biases of output tile T of a hidden layer, for a lane of half hf, in slot order: units
-// 32 T + 8 hf + e and 32 T + 16 + 8 hf + e (e < 8), four 16-byte LDS reads.
-__device__ __forceinline__ void load_bias16(const float *bias, int T, int hf, float *b)
+// The 16 biases of output tile T of a hidden layer, for a lane of half hf, in slot order (units
+// 32 T + 8 hf + e and 32 T + 16 + 8 hf + e, e < 8: the order of the MFMA's output registers), as the
+// accumulator the tile's first MFMA starts from, so that the matrix unit adds them; four 16-byte
+// LDS reads.
+__device__ __forceinline__ f32x16 load_bias16(const float *bias, int T, int hf)
 {
     const f32x4 *p0 = reinterpret_cast<const f32x4 *>(bias + 32 * T + 8 * hf);
     const f32x4 *p1 = reinterpret_cast<const f32x4 *>(bias + 32 * T + 16 + 8 * hf);
     const f32x4 v0 = p0[0], v1 = p0[1], v2 = p1[0], v3 = p1[1];
+    f32x16 b;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         b[e] = v0[e];
@@ -191,6 +194,7 @@ __device__ __forceinline__ void load_bias16(const float *bias, int T, int hf, fl
         b[8 + e] = v2[e];
         b[12 + e] = v3[e];
     }
+    return b;
 }
 
 // LDS operands are requested before the MFMAs that need them and the activations of the previous
@@ -198,13 +202,13 @@ __device__ __forceinline__ void load_bias16(const float *bias, int T, int hf, fl
 // each would expose its full LDS latency.
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// SiLU of one output tile's pre-activations z (bias included)
 template <bool TRAIN>
-__device__ __forceinline__ void activate16(const f32x16 &acc, const float *bv, int T, float *d, uint32_t *h)
+__device__ __forceinline__ void activate16(const f32x16 &z, int T, float *d, uint32_t *h)
 {
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
-        const float za = acc[q] + bv[q];
-        const float zb = acc[q + 1] + bv[q + 1];
+        const float za = z[q], zb = z[q + 1];
         const float sa = sigm(za), sb = sigm(zb);
         const float ha = za * sa, hb = zb * sb;
         if (TRAIN) {
@@ -215,29 +219,25 @@ __device__ __forceinline__ void activate16(const f32x16 &acc, const float *bv, i
     }
 }
 
-// Layer 1 (16 features -> 64 units) and layer 2 (64 -> 64) of 32 samples: MFMA, bias, SiLU, with
-// the SiLU derivatives when TRAIN.  Each tile's operands and biases are read from LDS before its
-// MFMAs are issued.
+// Layer 1 (16 features -> 64 units) and layer 2 (64 -> 64) of 32 samples: MFMA (starting from the
+// biases), SiLU, with the SiLU derivatives when TRAIN.  Each tile's operands and biases are read
+// from LDS before its MFMAs are issued.
 template <bool TRAIN>
 __device__ __forceinline__ void layer1(const uint16_t *Wbf, const float *sbias, const bf16x8 &bphi, int col, int hf,
                                        float *d1, uint32_t *h1)
 {
     bf16x8 a[2];
-    float bv[2][16];
-#pragma unroll
-    for (int T = 0; T < 2; ++T) {
-        a[T] = lds8(Wbf + kOffW1 + perm_row(32 * T + col) * 16 + 8 * hf);
-        load_bias16(sbias, T, hf, bv[T]);
-    }
-    sched_fence();
     f32x16 acc[2];
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
-        acc[T] = f32x16{};
-        acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[T], bphi, acc[T], 0, 0, 0);
+        a[T] = lds8(Wbf + kOffW1 + perm_row(32 * T + col) * 16 + 8 * hf);
+        acc[T] = load_bias16(sbias, T, hf);
     }
+    sched_fence();
 #pragma unroll
-    for (int T = 0; T < 2; ++T) activate16<TRAIN>(acc[T], bv[T], T, d1, h1);
+    for (int T = 0; T < 2; ++T) acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[T], bphi, acc[T], 0, 0, 0);
+#pragma unroll
+    for (int T = 0; T < 2; ++T) activate16<TRAIN>(acc[T], T, d1, h1);
 }
 
 template <bool TRAIN>
@@ -247,16 +247,14 @@ __device__ __forceinline__ void layer2(const uint16_t *Wbf, const float *sbias, 
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
         bf16x8 a[4];
-        float bv[16];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) a[kk] = lds8(Wbf + kOffW2 + m64(perm_row(32 * T + col), 16 * kk + 8 * hf));
-        load_bias16(sbias + 64, T, hf, bv);
+        f32x16 acc = load_bias16(sbias + 64, T, hf);
         sched_fence();
-        f32x16 acc = {};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk], pack4(h1 + 4 * kk), acc, 0, 0, 0);
-        activate16<TRAIN>(acc, bv, T, d2, h2);
+        activate16<TRAIN>(acc, T, d2, h2);
     }
 }
 
@@ -559,18 +557,25 @@ __device__ __forceinline__ bf16x4 lds_tr4(const uint8_t *p)
 }
 
 // 16x16x32 MFMA operand of a staged hidden-unit array: unit 16 b + lane % 16, samples 8 (lane / 16)
-// + 0 .. 7.  Lane 4 e + q of a group addresses units 16 b + 4 q .. + 3 of sample 8 (lane / 16) + 4 h + e.
-__device__ __forceinline__ bf16x8 tr_units(const uint16_t *arr, int b, int lane)
+// + 0 .. 7.  Lane 4 e + q of a group addresses units 16 b + 4 q .. + 3 of sample r = 8 (lane / 16)
+// + 4 h + e, i.e. the 8-byte half q % 2 of chunk (2 b + q / 2) ^ swz(r).  With r % 4 = e and
+// (r / 4) % 2 = h that is chunk 2 b ^ y0 ^ h of row r0 + 4 h, where the lane constants are
+// r0 = 8 (lane / 16) + e and y0 = q / 2 ^ 2 e.
+struct TrLane {
+    int row0;   // byte offset of row r0 plus the lane's 8-byte half
+    int y0;
+};
+__device__ __forceinline__ TrLane tr_lane(int lane)
 {
     const int G = lane >> 4, s = lane & 15;
-    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr);
-    bf16x4 v[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = 8 * G + 4 * h + (s >> 2);
-        v[h] = lds_tr4(base + r * 128 + (((2 * b + ((s & 3) >> 1)) ^ swz(r)) << 4) + ((s & 1) << 3));
-    }
-    return __builtin_shufflevector(v[0], v[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    return TrLane{(8 * G + (s >> 2)) * 128 + ((s & 1) << 3), ((s & 3) >> 1) ^ ((s >> 2) << 1)};
+}
+__device__ __forceinline__ bf16x8 tr_units(const uint16_t *arr, int b, const TrLane &t)
+{
+    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr) + t.row0;
+    const bf16x4 v0 = lds_tr4(base + (((2 * b) ^ t.y0) << 4));
+    const bf16x4 v1 = lds_tr4(base + 512 + (((2 * b) ^ t.y0 ^ 1) << 4));
+    return __builtin_shufflevector(v0, v1, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // Feature rows: 16 values (32 bytes) per sample, chunk c (features 8 c .. 8 c + 7) of row r at
@@ -580,17 +585,14 @@ __device__ __forceinline__ void stage_phi(uint16_t *arr, int col, int hf, const 
     const u32x4 v = {phi4[0], phi4[1], phi4[2], phi4[3]};
     *reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(arr) + col * 32 + ((hf ^ ((col >> 2) & 1)) << 4)) = v;
 }
+// (sample r = 8 (lane / 16) + 4 h + e, chunk q / 2 ^ h)
 __device__ __forceinline__ bf16x8 tr_phi(const uint16_t *arr, int lane)
 {
-    const int G = lane >> 4, s = lane & 15;
-    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr);
-    bf16x4 v[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = 8 * G + 4 * h + (s >> 2);
-        v[h] = lds_tr4(base + r * 32 + ((((s & 3) >> 1) ^ ((r >> 2) & 1)) << 4) + ((s & 1) << 3));
-    }
-    return __builtin_shufflevector(v[0], v[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const int G = lane >> 4, s = lane & 15, x = (s & 3) >> 1;
+    const uint8_t *base = reinterpret_cast<const uint8_t *>(arr) + (8 * G + (s >> 2)) * 32 + ((s & 1) << 3);
+    const bf16x4 v0 = lds_tr4(base + (x << 4));
+    const bf16x4 v1 = lds_tr4(base + 128 + ((x ^ 1) << 4));
+    return __builtin_shufflevector(v0, v1, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // Optimiser state of one parameter: FP32 master weight and the two Adam moments, read and written
@@ -681,13 +683,14 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             int cl = lane, cw = wave;
             asm volatile("" : "+v"(cl), "+v"(cw));
             const int r2 = (cw & 3) >> 1, c2 = cw & 1, tt = cw & 3, vv = 4 * (cw >> 2);
+            const TrLane tl = tr_lane(cl);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 bf16x8 a[2], b[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    a[i] = tr_units(stg(0, vv + v), 2 * r2 + i, cl);
-                    b[i] = tr_units(stg(1, vv + v), 2 * c2 + i, cl);
+                    a[i] = tr_units(stg(0, vv + v), 2 * r2 + i, tl);
+                    b[i] = tr_units(stg(1, vv + v), 2 * c2 + i, tl);
                 }
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
@@ -695,7 +698,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                     for (int j = 0; j < 2; ++j)
                         g2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], g2[i][j], 0, 0, 0);
                 gb2v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c2 ? a[1] : a[0], ones, gb2v, 0, 0, 0);
-                const bf16x8 a1 = tr_units(stg(2, vv + v), tt, cl);
+                const bf16x8 a1 = tr_units(stg(2, vv + v), tt, tl);
                 const bf16x8 b1 = tr_phi(sphi[vv + v], cl);
                 g1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, g1, 0, 0, 0);
                 gb1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, ones, gb1v, 0, 0, 0);
@@ -772,6 +775,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 const int G = dl >> 4;
                 const float *d3s = sd3[dw];
                 const uint16_t *h2s = stg(3, dw);
+                const TrLane tl = tr_lane(dl);
                 const f32x4 da0 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G);
                 const f32x4 da1 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G + 4);
                 const f32x4 db0 = *reinterpret_cast<const f32x4 *>(d3s + 32 + 8 * G);
@@ -788,7 +792,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const u16x8 hv = __builtin_bit_cast(u16x8, tr_units(h2s, b, dl));
+                    const u16x8 hv = __builtin_bit_cast(u16x8, tr_units(h2s, b, tl));
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const float h = from_bf16(hv[e]);

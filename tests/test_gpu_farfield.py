@@ -472,6 +472,69 @@ def _eval(torch, P, job, cfg, model, counts, lost, flags=0, dump=False):
     return (c, ry.cpu().numpy(), rp.cpu().numpy()) if dump else c
 
 
+def test_ragged_window_every_ray_matches_oracle():
+    # A window that is no multiple of the tile (150 x 100 rays: tiles of 64 or 22 by 64 or 36 rays).
+    # Every ray: with the network off, y = lambda x - (affine base + near field) against the FP64
+    # oracle; the network's own output per ray against the bfloat16-emulating oracle; the exact
+    # far-field samples of the smallest tile against the oracle's.  Every dump slot is written and
+    # the map is the histogram of the dumped pixels.
+    torch, P = _env()
+    w = _small_field()
+    win = ((4001, 4030), (150, 100))
+    (wl1, wl2), (wn1, wn2) = win
+    ntx, nty = 3, 2
+    job, cfg, model, dg, dt, u, p0, keep = _fit(torch, P, w, win, steps=40, debug=True)
+    lenses, counts, lost = keep[0], keep[1], keep[2]
+    hdr, wts, bias = _records(model, ntx * nty)
+    cs, ys, ps = _eval(torch, P, job, cfg, model, counts, lost, dump=True)
+    ls = int(lost.item())
+    _, ya, _ = _eval(torch, P, job, cfg, model, counts, lost, flags=P._abi.RS_FLAG_AFFINE_ONLY, dump=True)
+    assert np.isfinite(ys).all() and np.isfinite(ya).all() and np.all(ps >= -1)
+    assert int(cs.sum()) + ls == wn1 * wn2
+    assert np.array_equal(cs.ravel(), np.bincount(ps[ps >= 0], minlength=cs.size))
+    lam = (1.0 - w.gamma - w.kappa_c, 1.0 + w.gamma - w.kappa_c)
+    xs1 = oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0]).astype(np.float64)
+    xs2 = oracle.axis(w.grid_lo[1], w.grid_hi[1], w.grid_n[1]).astype(np.float64)
+    worst_near = worst_net = 0.0
+    for ty in range(nty):
+        for tx in range(ntx):
+            t = ty * ntx + tx
+            lo, hi, c, h, (i0, n) = off.tile_rect(w, win, TILE, tx, ty)
+            assert tuple(n) == (64 if tx < 2 else 22, 64 if ty < 1 else 36)
+            assert np.array_equal(hdr[t, 0:2], c) and np.array_equal(hdr[t, 2:4], h)
+            near = off.near_mask(w.lenses, lo, hi, R_NEAR)
+            a0, J = off.affine_base(np.ascontiguousarray(w.lenses[~near]), c)
+            iy, ix = np.divmod(np.arange(n[0] * n[1]), n[0])
+            g1, g2 = i0[0] + ix, i0[1] + iy
+            x = np.stack([xs1[g1], xs2[g2]], 1)
+            Ln = np.ascontiguousarray(w.lenses[near])
+            y_o = np.stack([lam[0] * x[:, 0], lam[1] * x[:, 1]], 1) - (a0[None, :] + (x - c[None, :]) @ J.T
+                                                                      + oracle.deflect(Ln, x))
+            rw = (g2 - wl2) * wn1 + (g1 - wl1)
+            Lf = Ln.astype(np.float64)
+            s = np.sum(Lf[None, :, 2] / np.hypot(x[:, None, 0] - Lf[None, :, 0], x[:, None, 1] - Lf[None, :, 1]), 1)
+            bound = 48 * 2.0 ** -24 * s[:, None] + 1e-9 * (1 + np.abs(y_o))
+            worst_near = max(worst_near, float(np.max(np.abs(ya[rw] - y_o) / bound)))
+            p = _assemble(wts[t], bias[t])
+            uu = (x - c[None, :]) / h[None, :]
+            o_or, _ = mlp.forward(p, uu, bf=True)
+            o_gpu = (ya[rw] - ys[rw]) / hdr[t, 9]
+            worst_net = max(worst_net, float(np.max(np.abs(o_gpu - o_or) / (network_bound(p, uu) + 1e-9))))
+    print(f"ragged window: affine + near field max err / bound {worst_near:.3f}, network {worst_net:.3f}")
+    assert worst_near <= 1.0 and worst_net <= 1.0
+    # exact far-field samples of the 22 x 36-ray corner tile
+    res, st, _, _, far = off.tile_targets(w, win, TILE, 2, 1, R_NEAR, u, threads=16)
+    lo, hi, c, h, _ = off.tile_rect(w, win, TILE, 2, 1)
+    pts = (c[None, :] + u.astype(np.float64) * h[None, :]).astype(np.float32).astype(np.float64)
+    Lf = w.lenses[far].astype(np.float64)
+    sm = np.zeros(len(pts))
+    for c0 in range(0, len(Lf), 2048):
+        Lc = Lf[c0:c0 + 2048]
+        sm += np.sum(Lc[None, :, 2] / np.hypot(pts[:, None, 0] - Lc[None, :, 0], pts[:, None, 1] - Lc[None, :, 1]), 1)
+    err = np.abs(dt.cpu().numpy()[5] - res)
+    assert np.all(err <= (8 + 16) * 2.0 ** -24 * sm[:, None] + 2.0 ** -23 * np.abs(res) + 1e-12)
+
+
 def _moving_job(P, job, w, lenses, counts, lost, vel, t):
     return P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
                       counts, lost, window=((job.grid.win_lo[0], job.grid.win_lo[1]),

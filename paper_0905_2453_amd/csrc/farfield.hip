@@ -379,30 +379,37 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 
 // ---------------------------------------------------------------- fit: exact far-field samples
 
-// Workgroup (tile, part): 256 threads x S samples = samples [256 S part, 256 S (part + 1)).
-// Samples come in groups g of 256: sample 64 (4 g + k) + i, k = 0..3, i = 0..63.  With S = 4,
-// thread i of wave w takes k = 0..3 of group 4 part + w; with S = 2 (twice the workgroups, for
-// fits with few tiles), k = 2 (w & 1) + {0, 1} of group 2 part + (w >> 1).
+// Workgroup (tile, part): 256 threads x 4 samples = samples [1024 part, 1024 (part + 1)).
+// Samples come in groups g of 256: sample 64 (4 g + k) + i, k = 0..3, i = 0..63; thread i of wave w
+// takes k = 0..3 of group 4 part + w.
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
 // of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
-// Samples k = (0, 1) and (2, 3) share one reciprocal per lens, as the plain path's row pairs do
-// (a far lens is at least r_near from every sample, so no pair product is zero).
+// The four samples of a thread share one reciprocal per lens (simultaneous inversion of the
+// product of their four squared distances: a far lens is at least r_near from every sample, so no
+// product is zero).  Coordinates are staged scaled by 2^-4 (exact), which keeps that product in the
+// float32 range for lenses up to about 1e6 from the samples (6.6e4 unscaled); a lens farther than
+// that (its deflection there is below 1e-6 m) gets a zero reciprocal and is dropped.  The sums are
+// scaled back by 2^4 with the FP64 combination.  The samples' error bound stays that of the plain path (far
+// below the bfloat16 precision of the network they train).
 // GRID: the samples of a thread share their first coordinate, so x - x_l and its square are
-// computed once.  Every sample sees the same operations whatever S and GRID are (the targets
-// are bit-identical).
-template <int S>
+// computed once; every sample sees the same operations either way (the targets are
+// bit-identical), and in every launch (the layout does not depend on the number of tiles).
 __device__ __forceinline__ int sample_index(int part, int k, int tid)
 {
     const int w = tid >> 6, lane = tid & 63;
-    if (S == 4) return (16 * part + 4 * w + k) * 64 + lane;
-    return (4 * (2 * part + (w >> 1)) + 2 * (w & 1) + k) * 64 + lane;
+    return (16 * part + 4 * w + k) * 64 + lane;
 }
 
-template <bool GRID, int S>
+constexpr float kSampleScale = 0.0625f;   // 2^-4
+// Zero-mass padding of the sample kernel, in its scaled coordinates: its squared distance (~2e18)
+// keeps every pair product finite, so the quad product overflows to a zero reciprocal and every
+// padding term is exactly 0 (never 0 x inf).
+constexpr float kSamplePad = 1.0e9f;
+
+template <bool GRID>
 __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
 {
-    static_assert(S == 2 || S == 4, "samples per thread");
-    constexpr int LT = 256, T = 16;
+    constexpr int LT = 256, T = 16, S = 4;
     __shared__ float4 s_lens[2][LT];
     const uint32_t tile = blockIdx.x / (uint32_t)parts, part = blockIdx.x % (uint32_t)parts;
     double lo[2], hi[2], c[2], hw[2];
@@ -411,18 +418,19 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
     tile_geom(f, tile, lo, hi, c, hw, i0, n);
     const double rn2 = f.r_near * f.r_near;
     const int tid = threadIdx.x;
-    float px[S], py[S];
+    float px[S], py[S];   // sample positions (float32), scaled by 2^-4
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index<S>(part, k, tid);
-        px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]);
-        py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]);
+        const int si = sample_index(part, k, tid);
+        px[k] = (float)(c[0] + (double)f.samples[2 * si] * hw[0]) * kSampleScale;
+        py[k] = (float)(c[1] + (double)f.samples[2 * si + 1] * hw[1]) * kSampleScale;
     }
     double A1[S] = {}, A2[S] = {};
     auto fetch = [&](int64_t i) -> float4 {
-        if (i >= f.n_lens) return make_float4(kPadCoord, kPadCoord, 0.f, 0.f);
+        if (i >= f.n_lens) return make_float4(kSamplePad, kSamplePad, 0.f, 0.f);
         const float4 l = f.lenses[i];
-        return is_near(l.x, l.y, lo, hi, rn2) ? make_float4(kPadCoord, kPadCoord, 0.f, 0.f) : l;
+        return is_near(l.x, l.y, lo, hi, rn2) ? make_float4(kSamplePad, kSamplePad, 0.f, 0.f)
+                                              : make_float4(l.x * kSampleScale, l.y * kSampleScale, l.z, l.w);
     };
     const int64_t n_tiles = (f.n_lens + LT - 1) / LT;
     float4 reg = n_tiles > 0 ? fetch(tid) : make_float4(0, 0, 0, 0);
@@ -440,18 +448,21 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
                 const float4 l = L[r + j];
                 // GRID: the four samples share px[0]
                 const float dxs = px[0] - l.x, dxs2 = dxs * dxs;
+                float dx[S], dy[S], q[S];
 #pragma unroll
-                for (int k = 0; k < S; k += 2) {
-                    const float dxa = GRID ? dxs : px[k] - l.x, dya = py[k] - l.y;
-                    const float dxb = GRID ? dxs : px[k + 1] - l.x, dyb = py[k + 1] - l.y;
-                    const float ra = fmaf(dya, dya, GRID ? dxs2 : dxa * dxa);
-                    const float rb = fmaf(dyb, dyb, GRID ? dxs2 : dxb * dxb);
-                    const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
-                    const float da = g * rb, db = g * ra;
-                    s1[k] = j == 0 ? da * dxa : fmaf(da, dxa, s1[k]);
-                    s2[k] = j == 0 ? da * dya : fmaf(da, dya, s2[k]);
-                    s1[k + 1] = j == 0 ? db * dxb : fmaf(db, dxb, s1[k + 1]);
-                    s2[k + 1] = j == 0 ? db * dyb : fmaf(db, dyb, s2[k + 1]);
+                for (int k = 0; k < S; ++k) {
+                    dx[k] = GRID ? dxs : px[k] - l.x;
+                    dy[k] = py[k] - l.y;
+                    q[k] = fmaf(dy[k], dy[k], GRID ? dxs2 : dx[k] * dx[k]);
+                }
+                const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                const float g01 = g * p23, g23 = g * p01;
+                const float d[S] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    s1[k] = j == 0 ? d[k] * dx[k] : fmaf(d[k], dx[k], s1[k]);
+                    s2[k] = j == 0 ? d[k] * dy[k] : fmaf(d[k], dy[k], s2[k]);
                 }
             }
 #pragma unroll
@@ -465,12 +476,14 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
     }
     const double *h = tile_hdr(f, tile);
     const double a01 = h[4], a02 = h[5], j11 = h[6], j12 = h[7], j22 = h[8];
+    // m (x - x_l) / r^2 of the scaled coordinates is 2^4 times the true term
+    constexpr double kBack = kRcpBiasComp / 16.0;
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const int si = sample_index<S>(part, k, tid);
-        const double d1 = (double)px[k] - c[0], d2 = (double)py[k] - c[1];
-        const double r1 = A1[k] * kRcpBiasComp - (a01 + j11 * d1 + j12 * d2);
-        const double r2 = A2[k] * kRcpBiasComp - (a02 + j12 * d1 + j22 * d2);
+        const int si = sample_index(part, k, tid);
+        const double d1 = (double)(px[k] * 16.0f) - c[0], d2 = (double)(py[k] * 16.0f) - c[1];
+        const double r1 = A1[k] * kBack - (a01 + j11 * d1 + j12 * d2);
+        const double r2 = A2[k] * kBack - (a02 + j12 * d1 + j22 * d2);
         float *out = f.targets + ((size_t)tile * f.n_samples + si) * 2;
         out[0] = (float)r1;
         out[1] = (float)r2;
@@ -1286,21 +1299,11 @@ hipError_t launch_ff_fit(const FarArgs &f, uint64_t hash, hipStream_t s)
         hipSuccess)
         return e;
     if ((e = launch_affine(f, nt, s)) != hipSuccess) return e;
-    // four samples per thread share the most work; with fewer than 4096 such workgroups, two per
-    // thread double the workgroups and keep every compute unit full (same targets either way)
-    const int parts4 = f.n_samples / 1024;
-    if ((int64_t)nt * parts4 >= 4096) {
-        if (f.grid_samples)
-            hipLaunchKernelGGL((k_ff_samples<true, 4>), dim3(nt * (uint32_t)parts4), dim3(256), 0, s, f, parts4);
-        else
-            hipLaunchKernelGGL((k_ff_samples<false, 4>), dim3(nt * (uint32_t)parts4), dim3(256), 0, s, f, parts4);
-    } else {
-        const int parts2 = 2 * parts4;
-        if (f.grid_samples)
-            hipLaunchKernelGGL((k_ff_samples<true, 2>), dim3(nt * (uint32_t)parts2), dim3(256), 0, s, f, parts2);
-        else
-            hipLaunchKernelGGL((k_ff_samples<false, 2>), dim3(nt * (uint32_t)parts2), dim3(256), 0, s, f, parts2);
-    }
+    const int parts = f.n_samples / 1024;
+    if (f.grid_samples)
+        hipLaunchKernelGGL(k_ff_samples<true>, dim3(nt * (uint32_t)parts), dim3(256), 0, s, f, parts);
+    else
+        hipLaunchKernelGGL(k_ff_samples<false>, dim3(nt * (uint32_t)parts), dim3(256), 0, s, f, parts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ff_normalize, dim3(nt), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -643,3 +643,103 @@ def test_shared_x_samples_fit_is_bit_identical():
     with pytest.raises(P.RayShootError) as ei:
         P.farfield_fit(job, cfg, model, ws)
     assert ei.value.status == -1
+
+
+def _full_size_case(w, win, tile, n_samples, n_tiles_eval, rays_per_tile, seed):
+    """Fit the window in the bench's launch configuration (quads sharing x, 2000 Adam steps of 512),
+    evaluate a seeded sample of tiles with per-ray dumps, network on and off, and check sampled rays
+    of every evaluated tile: y with the network off against the FP64 oracle (affine base + near
+    field), the network's own output against the bfloat16-emulating oracle on the model's weights."""
+    torch, P = _env()
+    dev = torch.device("cuda:0")
+    (wl1, wl2), (wn1, wn2) = win
+    lenses = torch.from_numpy(w.lenses).to(dev)
+    counts = torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev)
+    lost = torch.zeros(1, dtype=torch.int64, device=dev)
+    job = P.make_job(lenses, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                     counts, lost, window=win)
+    ut = torch.from_numpy(synth.fit_samples_quads(7, n_samples)).to(dev)
+    pt = torch.from_numpy(synth.init_params(7)).to(dev)
+    cfg = P.ff_config(ut, pt, tile_rays=tile, r_near=R_NEAR, steps=2000, batch=512, lr=1e-2, shared_x=True)
+    model = torch.zeros(P.farfield_model_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    fws = torch.empty(P.farfield_fit_workspace_bytes(job, cfg), dtype=torch.uint8, device=dev)
+    P.farfield_fit(job, cfg, model, fws)
+    torch.cuda.synchronize()
+    del fws
+    ntx, nty = (wn1 + tile[0] - 1) // tile[0], (wn2 + tile[1] - 1) // tile[1]
+    tiles = synth.sample_indices(seed, ntx * nty, n_tiles_eval)
+    tt = torch.from_numpy(tiles.astype(np.int32)).to(dev)
+    ecfg = P.ff_config(ut, pt, tile_rays=tile, r_near=R_NEAR, steps=2000, batch=512, lr=1e-2, shared_x=True,
+                       eval_tiles=tt)
+    # rays: rays_per_tile seeded rays of every evaluated tile (window-relative indices)
+    picks = []
+    for k, t in enumerate(tiles):
+        tx, ty = int(t % ntx), int(t // ntx)
+        _, _, _, _, (i0, n) = off.tile_rect(w, win, tile, tx, ty)
+        r = synth.sample_indices(seed + 1 + k, n[0] * n[1], rays_per_tile)
+        picks.append((t, tx, ty, i0, n, (i0[1] - wl2 + r // n[0]) * wn1 + (i0[0] - wl1 + r % n[0])))
+    idx = torch.from_numpy(np.concatenate([p[5] for p in picks])).to(dev)
+    ry = torch.full((wn1 * wn2, 2), float("nan"), dtype=torch.float64, device=dev)
+    rp = torch.full((wn1 * wn2,), -7, dtype=torch.int32, device=dev)
+    ews = torch.empty(P.farfield_eval_workspace_bytes(job, ecfg), dtype=torch.uint8, device=dev)
+    got = []
+    for flags in (0, P._abi.RS_FLAG_AFFINE_ONLY):
+        o = P.Opts()
+        o.ray_y, o.ray_pix, o.flags = ry.data_ptr(), rp.data_ptr(), flags
+        P.farfield_eval(job, ecfg, model, ews, o)
+        torch.cuda.synchronize()
+        got.append(ry[idx].cpu().numpy())
+    del ry, rp
+    ys, ya = got
+    assert np.isfinite(ys).all() and np.isfinite(ya).all()
+    n_tiles = ntx * nty
+    mm = model.cpu().numpy()
+    rec = (len(mm) - 256) // n_tiles
+    lam = (1.0 - w.gamma - w.kappa_c, 1.0 + w.gamma - w.kappa_c)
+    xs1 = oracle.axis(w.grid_lo[0], w.grid_hi[0], w.grid_n[0]).astype(np.float64)
+    xs2 = oracle.axis(w.grid_lo[1], w.grid_hi[1], w.grid_n[1]).astype(np.float64)
+    boff = 128 + ((2 * mlp.N_PARAMS + 15) // 16) * 16
+    worst_near = worst_net = 0.0
+    at = 0
+    for t, tx, ty, i0, n, rw in picks:
+        sl = slice(at, at + len(rw))
+        at += len(rw)
+        base = 256 + int(t) * rec
+        hdr = mm[base: base + 80].view(np.float64)
+        wts = (mm[base + 128: base + 128 + 2 * mlp.N_PARAMS].view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+        bias = mm[base + boff: base + boff + 520].view(np.float32)
+        lo, hi, c, h, _ = off.tile_rect(w, win, tile, tx, ty)
+        assert np.array_equal(hdr[0:2], c) and np.array_equal(hdr[2:4], h)
+        g1, g2 = wl1 + rw % wn1, wl2 + rw // wn1
+        x = np.stack([xs1[g1], xs2[g2]], 1)
+        near = off.near_mask(w.lenses, lo, hi, R_NEAR)
+        a0, J = off.affine_base(np.ascontiguousarray(w.lenses[~near]), c)
+        Ln = np.ascontiguousarray(w.lenses[near])
+        y_o = np.stack([lam[0] * x[:, 0], lam[1] * x[:, 1]], 1) - (a0[None, :] + (x - c[None, :]) @ J.T
+                                                                  + oracle.deflect(Ln, x))
+        Lf = Ln.astype(np.float64)
+        s = np.sum(Lf[None, :, 2] / np.hypot(x[:, None, 0] - Lf[None, :, 0], x[:, None, 1] - Lf[None, :, 1]), 1)
+        bound = 48 * 2.0 ** -24 * s[:, None] + 1e-9 * (1 + np.abs(y_o))
+        worst_near = max(worst_near, float(np.max(np.abs(ya[sl] - y_o) / bound)))
+        p = _assemble(wts.astype(np.float64), bias)
+        uu = (x - c[None, :]) / h[None, :]
+        o_or, _ = mlp.forward(p, uu, bf=True)
+        o_gpu = (ya[sl] - ys[sl]) / hdr[9]
+        worst_net = max(worst_net, float(np.max(np.abs(o_gpu - o_or) / (network_bound(p, uu) + 1e-9))))
+    print(f"{w.name}: {len(tiles)} of {n_tiles} tiles, {at} rays: affine + near field max err / bound "
+          f"{worst_near:.3f}, network {worst_net:.3f}")
+    assert worst_near <= 1.0 and worst_net <= 1.0
+
+
+def test_full_size_farfield_sampled_rays():
+    # the 1e6-lens workload at full size: 8192^2 rays in 16384 tiles of 64^2, 4096 samples per tile
+    w = synth.workload_farfield()
+    _full_size_case(w, ((0, 0), (8192, 8192)), (64, 64), 4096, 64, 64, 51)
+
+
+def test_large_field_tile_config_sampled_rays():
+    # the 1e7-lens workload's field and launch configuration (1024^2-ray tiles, 1024 samples per
+    # tile) on a 4 x 4-tile window at the grid centre
+    w = synth.workload_large()
+    c = 32768 // 2 - 2048
+    _full_size_case(w, ((c, c), (4096, 4096)), (1024, 1024), 1024, 16, 64, 61)

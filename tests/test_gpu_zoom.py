@@ -87,6 +87,17 @@ def test_zoom_equals_fine_grid_paper_field(block, jitter):
     assert st["cells_kept"] < 0.06 * st["cells"] and st["slots_shot"] < 0.06 * st["slots"]
 
 
+def test_zoom_equals_fine_grid_bench_configuration():
+    # the configuration the benchmark times: the paper workload's field and shooting region at 4x
+    # the ray density per axis (16384^2 fine rays), a 2.5 x 2.5 window at 256^2, automatic cells
+    w = synth.workload_paper()
+    fine = (4 * w.grid_n[0], 4 * w.grid_n[1])
+    cp, cz, st = _run(w, fine, (-1.25, -1.25), (1.25, 1.25), (256, 256))
+    print("bench zoom configuration:", st, "counts", int(cp.sum()))
+    assert cp.sum() > 0 and np.array_equal(cp, cz)
+    assert st["slots_shot"] < 0.05 * st["slots"]
+
+
 @pytest.mark.parametrize("block,jitter,cell", [((2, 4), None, (5, 7)), ((1, 4), 29, (0, 0)), ((4, 2), 3, (3, 9))])
 def test_zoom_odd_window_blocks_and_jitter(block, jitter, cell):
     # a window starting on an odd row and column, several lane shapes, jittered rays and odd cell

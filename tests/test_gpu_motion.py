@@ -131,3 +131,53 @@ def test_zoom_on_moving_field_equals_fine_grid():
         torch.cuda.synchronize()
         out.append(c.cpu().numpy().view(np.uint32).copy())
     assert out[0].sum() > 0 and np.array_equal(out[0], out[1])
+
+
+def test_frame_batch_full_size_sampled_parity():
+    # The benchmark's frame leg at full size: the paper workload (1e5 lenses, 4096^2 rays, 1024^2
+    # map) at times 0..7 with a velocity dispersion of 0.05 per axis, one persistent launch; every
+    # frame bit-identical to its moving job shot alone, and 2048 seeded rays of each frame's dump
+    # against the FP64 oracle on the advanced field (switches counted over all frames against the
+    # 1e-5 bar with its Poisson allowance).
+    import math
+    torch, P = _env()
+    w = synth.workload_paper()
+    v = synth.lens_velocities(13, w.n_lens, 0.05)
+    dev = torch.device("cuda:0")
+    L, V = _dev(w.lenses), _dev(v)
+    times = [float(k) for k in range(8)]
+    maps = [torch.zeros((w.map_n[1], w.map_n[0]), dtype=torch.int32, device=dev) for _ in times]
+    losts = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in times]
+    jobs = [P.make_job(L, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n,
+                       maps[k], losts[k], velocities=V, time=t) for k, t in enumerate(times)]
+    ws = torch.empty(P.batched_workspace_bytes(jobs), dtype=torch.uint8, device=dev)
+    P.shoot_batched(jobs, ws)
+    torch.cuda.synchronize()
+    del ws
+    nr = w.n_rays
+    n_sw = n_in = 0
+    for k, t in enumerate(times):
+        c = torch.zeros_like(maps[k])
+        lo = torch.zeros(1, dtype=torch.int64, device=dev)
+        j = P.make_job(L, w.kappa_c, w.gamma, w.grid_lo, w.grid_hi, w.grid_n, w.map_lo, w.map_hi, w.map_n, c, lo,
+                       velocities=V, time=t)
+        ry = torch.empty((nr, 2), dtype=torch.float64, device=dev)
+        rp = torch.empty((nr,), dtype=torch.int32, device=dev)
+        o = P.Opts()
+        o.ray_y, o.ray_pix = ry.data_ptr(), rp.data_ptr()
+        wsj = torch.empty(P.workspace_bytes(j, o), dtype=torch.uint8, device=dev)
+        P.shoot_job(j, wsj, o)
+        torch.cuda.synchronize()
+        assert torch.equal(c, maps[k]) and int(lo.item()) == int(losts[k].item()), t
+        assert int(c.sum().item()) + int(lo.item()) == nr
+        idx = synth.sample_indices(200 + k, nr, 2048)
+        p_g = rp[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.int64)
+        del ry, rp, wsj
+        wt = synth.Workload(w.name, oracle.lenses_at(w.lenses, v, t), w.kappa_c, w.gamma, w.grid_lo, w.grid_hi,
+                            w.grid_n, w.map_lo, w.map_hi, w.map_n)
+        _, p_o = oracle.trace_parallel(wt, idx, threads=16)
+        n_sw += int(np.sum(p_g != p_o))
+        n_in += int(np.sum((p_g >= 0) | (p_o >= 0)))
+    mean = 1e-5 * n_in
+    print(f"8 moving frames at full size: {n_sw} of {n_in} sampled rays in a map switch pixel")
+    assert n_sw <= mean + 3.0 * math.sqrt(mean)

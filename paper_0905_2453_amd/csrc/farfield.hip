@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) uint16_t W2T[64 * 64];
     __shared__ __attribute__((aligned(16))) float sbias[130];
-    __shared__ __attribute__((aligned(16))) float sW3[128];   // (W3[0][u], W3[1][u]) of unit u, bfloat16 values
+    __shared__ __attribute__((aligned(16))) uint32_t sW3p[64];   // bfloat16 pair (W3[0][u], W3[1][u]) of unit u
     // array a (0 dz2, 1 h1, 2 dz1, 3 h2) of wave v at sstage + (a kTrainWaves + v) kStageWords
     __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * kTrainWaves * kStageWords];
     __shared__ __attribute__((aligned(16))) uint16_t sphi[kTrainWaves][16 * 32];
@@ -663,7 +663,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
         if (p >= kOffW2 && p < kOffB2) W2T[m64((p - kOffW2) & 63, (p - kOffW2) >> 6)] = b;
         if (p >= kOffB1 && p < kOffW2) sbias[p - kOffB1] = w;
         if (p >= kOffB2 && p < kOffW3) sbias[64 + p - kOffB2] = w;
-        if (p >= kOffW3 && p < kOffB3) sW3[2 * ((p - kOffW3) & 63) + (p - kOffW3) / 64] = from_bf16(b);
+        if (p >= kOffW3 && p < kOffB3)
+            reinterpret_cast<uint16_t *>(sW3p)[2 * ((p - kOffW3) & 63) + (p - kOffW3) / 64] = b;
         if (p >= kOffB3) sbias[128 + p - kOffB3] = w;
     }
     // (the first round's barrier orders these stores before their use)
@@ -747,19 +748,24 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 d3s[col] = d30;
                 d3s[32 + col] = d31;
             }
-            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 (the bfloat16 weights as FP32 pairs)
+            // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 as one 32x32x16 MFMA per output tile: d3 enters
+            // as two bfloat16 terms hi + lo (equal to d3 within 2^-18 of it, far below the bfloat16
+            // rounding of dz2), k = 0..3 = (hi0, hi1, lo0, lo1) against (W3[0][u], W3[1][u]) twice in
+            // the rows of unit u (permuted like every hidden-producing layer, so the output registers
+            // are the lane's slots); k >= 4 is zero
+            const uint32_t d3hi = pk2(d30, d31);
+            const uint32_t d3lo = pk2(d30 - lo_bf16(d3hi), d31 - hi_bf16(d3hi));
+            const u32x4 bdv = {hf == 0 ? d3hi : 0u, hf == 0 ? d3lo : 0u, 0u, 0u};
             uint32_t dz2[16];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const f32x4 *wp = reinterpret_cast<const f32x4 *>(sW3 + 2 * (16 * g + 8 * hf));
+            for (int T = 0; T < 2; ++T) {
+                const uint32_t wp = hf == 0 ? sW3p[perm_row(32 * T + col)] : 0u;
+                const u32x4 av = {wp, wp, 0u, 0u};
+                const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                           __builtin_bit_cast(bf16x8, bdv), f32x16{}, 0, 0, 0);
 #pragma unroll
-                for (int e = 0; e < 8; e += 2) {
-                    const int q = 8 * g + e;
-                    const f32x4 w = wp[e / 2];
-                    const float dha = fmaf(w[0], d30, w[1] * d31);
-                    const float dhb = fmaf(w[2], d30, w[3] * d31);
-                    dz2[q / 2] = pk2(dha * d2[q], dhb * d2[q + 1]);
-                }
+                for (int q = 0; q < 16; q += 2)
+                    dz2[(16 * T + q) / 2] = pk2(acc[q] * d2[16 * T + q], acc[q + 1] * d2[16 * T + q + 1]);
             }
             stage_row(z2s, col, hf, dz2);
             // dh1 = W2^T dz2 (rows permuted like a hidden-producing layer), dz1 = bf16(dh1 * silu'(z1))
@@ -974,6 +980,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             // b1, b2 and the two layer-3 weights of unit 8 w + lane
             const int un = 8 * wv + ln;
             const int ps[4] = {kOffB1 + un, kOffB2 + un, kOffW3 + un, kOffW3 + 64 + un};
+            uint32_t w3pair = 0u;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const AdamState s1 = adam(st[12 + k], gr[12 + k]);
@@ -982,8 +989,9 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
                 const uint16_t b = to_bf16(s1.w);
                 Wbf[ps[k]] = b;
                 if (k < 2) sbias[64 * k + un] = s1.w;
-                else sW3[2 * un + k - 2] = from_bf16(b);
+                else w3pair |= (uint32_t)b << (16 * (k - 2));
             }
+            sW3p[un] = w3pair;
         } else if (wv == 0 && ln < 10) {
             const int p = kOffB3 + ln - 8;
             const AdamState s1 = adam(st[12], gr[12]);

@@ -647,7 +647,9 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
     // array a (0 dz2, 1 h1, 2 dz1, 3 h2) of wave v at sstage + (a kTrainWaves + v) kStageWords
     __shared__ __attribute__((aligned(16))) uint16_t sstage[4 * kTrainWaves * kStageWords];
     __shared__ __attribute__((aligned(16))) uint16_t sphi[kTrainWaves][16 * 32];
-    __shared__ __attribute__((aligned(16))) float sd3[kTrainWaves][2 * 32];
+    // per sample the bfloat16 terms of d3 = (o - t) / B: (hi0, hi1, lo0, lo1), d3 = hi + lo within 2^-18
+    __shared__ __attribute__((aligned(16))) uint32_t sd3x[kTrainWaves][2 * 32];
+    __shared__ __attribute__((aligned(16))) uint32_t szero[2];
 
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hf = lane >> 5, col = lane & 31;
@@ -674,7 +676,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
     // owned blocks: dW2 rows 32 R .. + 32, columns 32 C .. + 32 (R, C from w % 4) and the dW1 rows
     // 16 (w % 4) .. + 16, both over the samples of waves 4 (w / 4) .. + 3; b2 of rows 32 R + 16 C .. + 16
     uint16_t *z2s = stg(0, wave), *h1s = stg(1, wave), *z1s = stg(2, wave), *h2s = stg(3, wave);
-    float *d3s = sd3[wave];
+    uint32_t *d3x = sd3x[wave];
+    if (tid < 2) szero[tid] = 0u;
     const u32x4 ones_u = {0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u};
     const bf16x8 ones = __builtin_bit_cast(bf16x8, ones_u);
     // the sample of the next round (samples of step t start at (t - 1) B mod N; B divides N), requested
@@ -689,8 +692,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
     fetch(0);
     for (int step = 1, i0 = 0; step <= f.steps; ++step, i0 = (i0 + f.batch == f.n_samples) ? 0 : i0 + f.batch) {
         f32x4 g2[2][2] = {}, g1 = {}, gb1v = {}, gb2v = {};
-        float w3a[8] = {};            // dW3 [block b][output o]: unit 16 b + lane % 16, samples 8 (lane / 16) ..
-        float gb3a0 = 0.f, gb3a1 = 0.f;
+        f32x4 w3m[4] = {}, gb3m = {};   // dW3 by unit block and b3: column lane % 16 < 4 holds d3 term n
         // owned weight-gradient blocks contracted over this round's samples, in wave order (the
         // operand addresses are recomputed here from laundered indices, not kept across the round)
         auto contract = [&]() __attribute__((always_inline)) {
@@ -744,10 +746,6 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             const float o0 = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
             const float o1 = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
             const float d30 = (o0 - t0) * inv_b, d31 = (o1 - t1) * inv_b;
-            if (hf == 0) {
-                d3s[col] = d30;
-                d3s[32 + col] = d31;
-            }
             // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 as one 32x32x16 MFMA per output tile: d3 enters
             // as two bfloat16 terms hi + lo (equal to d3 within 2^-18 of it, far below the bfloat16
             // rounding of dz2), k = 0..3 = (hi0, hi1, lo0, lo1) against (W3[0][u], W3[1][u]) twice in
@@ -756,6 +754,10 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             const uint32_t d3hi = pk2(d30, d31);
             const uint32_t d3lo = pk2(d30 - lo_bf16(d3hi), d31 - hi_bf16(d3hi));
             const u32x4 bdv = {hf == 0 ? d3hi : 0u, hf == 0 ? d3lo : 0u, 0u, 0u};
+            if (hf == 0) {
+                using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<u32x2 *>(d3x + 2 * col) = u32x2{d3hi, d3lo};
+            }
             uint32_t dz2[16];
 #pragma unroll
             for (int T = 0; T < 2; ++T) {
@@ -787,38 +789,26 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             stage_row(z1s, col, hf, dz1);
             // this wave's own staging: a wave-scope fence orders its stores and loads
             wave_sync();
-            // dW3 and b3 over this wave's samples: lane = unit 16 b + lane % 16, samples 8 G .. 8 G + 7
+            // dW3 and b3 over this wave's samples on the MFMA: A = h2 (unit 16 b + lane % 16, samples
+            // 8 (lane / 16) ..), B = the samples' d3 terms in columns 0..3 and zeros elsewhere, read
+            // transposed from the sample rows (lane 4 e + q of a group addresses the four terms of
+            // sample 8 (lane / 16) + 4 h + e when q = 0, a zero block otherwise); b3 is the same B
+            // against ones
             {
                 int dl = lane, dw = wave;
                 asm volatile("" : "+v"(dl), "+v"(dw));
-                const int G = dl >> 4;
-                const float *d3s = sd3[dw];
                 const uint16_t *h2s = stg(3, dw);
                 const TrLane tl = tr_lane(dl);
-                const f32x4 da0 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G);
-                const f32x4 da1 = *reinterpret_cast<const f32x4 *>(d3s + 8 * G + 4);
-                const f32x4 db0 = *reinterpret_cast<const f32x4 *>(d3s + 32 + 8 * G);
-                const f32x4 db1 = *reinterpret_cast<const f32x4 *>(d3s + 32 + 8 * G + 4);
+                const int s16 = dl & 15;
+                const uint8_t *row = reinterpret_cast<const uint8_t *>(sd3x[dw]) + (8 * (dl >> 4) + (s16 >> 2)) * 8;
+                const uint8_t *zb = reinterpret_cast<const uint8_t *>(szero);
+                const bool term = (s16 & 3) == 0;
+                const bf16x4 v0 = lds_tr4(term ? row : zb), v1 = lds_tr4(term ? row + 32 : zb);
+                const bf16x8 bd = __builtin_shufflevector(v0, v1, 0, 1, 2, 3, 4, 5, 6, 7);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gb3a0 += da0[e];
-                    gb3a1 += db0[e];
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gb3a0 += da1[e];
-                    gb3a1 += db1[e];
-                }
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const u16x8 hv = __builtin_bit_cast(u16x8, tr_units(h2s, b, tl));
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const float h = from_bf16(hv[e]);
-                        w3a[2 * b] = fmaf(e < 4 ? da0[e & 3] : da1[e & 3], h, w3a[2 * b]);
-                        w3a[2 * b + 1] = fmaf(e < 4 ? db0[e & 3] : db1[e & 3], h, w3a[2 * b + 1]);
-                    }
-                }
+                for (int b = 0; b < 4; ++b)
+                    w3m[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tr_units(h2s, b, tl), bd, w3m[b], 0, 0, 0);
+                gb3m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, bd, gb3m, 0, 0, 0);
             }
             __syncthreads();   // every wave's staging of this round is complete
             if (rd + 1 == rounds) break;
@@ -854,16 +844,12 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) st[k] = ost[pid[k] < 0 ? 0u : (uint32_t)pid[k]];
         contract();
-        // b3 and dW3: the four sample groups of each unit
+        // dW3 and b3 of output o = column o (hi term) + column o + 2 (lo term), held two lanes apart
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            w3a[k] += __shfl_xor(w3a[k], 16);
-            w3a[k] += __shfl_xor(w3a[k], 32);
-        }
-        gb3a0 += __shfl_xor(gb3a0, 16);
-        gb3a0 += __shfl_xor(gb3a0, 32);
-        gb3a1 += __shfl_xor(gb3a1, 16);
-        gb3a1 += __shfl_xor(gb3a1, 32);
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w3m[b][r] += __shfl_down(w3m[b][r], 2);
+        const float gb3 = gb3m[0] + __shfl_down(gb3m[0], 2);
         __syncthreads();   // the last round's readers are done: the staging area takes the partial sums
         float *xg1 = reinterpret_cast<float *>(sstage);    // [wave / 4][unit]: b1 partials
         float *xg2 = xg1 + 2 * 64;                         // [wave / 4][unit]: b2 partials
@@ -875,17 +861,13 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             *reinterpret_cast<f32x4 *>(xg1 + own * 64 + 16 * (wv & 3) + 4 * (ln >> 4)) = gb1v;
             *reinterpret_cast<f32x4 *>(xg2 + own * 64 + 32 * ((wv & 3) >> 1) + 16 * (wv & 1) + 4 * (ln >> 4)) = gb2v;
         }
-        if (ln < 16) {
+        if ((ln & 15) < 2) {
+            // lane (G, o): units 16 b + 4 G + r
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                xw3[(wv * 2 + 0) * 64 + 16 * b + ln] = w3a[2 * b];
-                xw3[(wv * 2 + 1) * 64 + 16 * b + ln] = w3a[2 * b + 1];
-            }
+            for (int b = 0; b < 4; ++b)
+                *reinterpret_cast<f32x4 *>(xw3 + (wv * 2 + (ln & 15)) * 64 + 16 * b + 4 * (ln >> 4)) = w3m[b];
         }
-        if (ln == 0) {
-            x3[wv * 2] = gb3a0;
-            x3[wv * 2 + 1] = gb3a1;
-        }
+        if (ln < 2) x3[wv * 2 + ln] = gb3;
         if (wv >= 4) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) x1[((wv - 4) * 64 + ln) * 4 + r] = g1[r];

@@ -157,10 +157,13 @@ __device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
 }
 
-// Layer 3 (64 units -> 2) over the lane's 32 units of its sample: word j of h2 holds slots 2j, 2j + 1,
-// the consecutive units 16 g + 8 hf + e, e + 1 (j = 4 g + e / 2), which pair with the consecutive
-// bfloat16 weights of W3's rows.  Two partial sums per output (even and odd g).
-__device__ __forceinline__ void layer3(const uint16_t *Wbf, const uint32_t *h2, int hf, float &po0, float &po1)
+// Layer 3 in training, where the forward pass holds no register to spare: the lane's 32 units of its
+// sample as bfloat16 pair dot products (word j of h2 holds slots 2j, 2j + 1, the consecutive units
+// 16 g + 8 hf + e, e + 1 with j = 4 g + e / 2, which pair with the consecutive weights of W3's rows),
+// two partial sums per output, then the two halves of the sample (lanes l and l ^ 32) in a fixed
+// order, plus b3.
+__device__ __forceinline__ void layer3_dot(const uint16_t *Wbf, const float *sbias, const uint32_t *h2, int hf,
+                                           float &o0, float &o1)
 {
     float a[2][2] = {};
 #pragma unroll
@@ -173,8 +176,29 @@ __device__ __forceinline__ void layer3(const uint16_t *Wbf, const uint32_t *h2, 
             a[g & 1][1] = dot2bf(h2[4 * g + j], w1[j], a[g & 1][1]);
         }
     }
-    po0 = a[0][0] + a[1][0];
-    po1 = a[0][1] + a[1][1];
+    const float p0 = a[0][0] + a[1][0], p1 = a[0][1] + a[1][1];
+    const float q0 = __shfl_xor(p0, 32), q1 = __shfl_xor(p1, 32);
+    o0 = (hf == 0 ? p0 + q0 : q0 + p0) + sbias[128];
+    o1 = (hf == 0 ? p1 + q1 : q1 + p1) + sbias[129];
+}
+
+// Layer 3 in evaluation (64 units -> 2) of 32 samples as four 32x32x16 MFMAs over the lane's activation pairs (the
+// B operand of layer 2's layout): rows 0 and 1 of A are W3's two rows (lanes 0, 1 and 32, 33), the
+// other rows read a 16-byte zero block; the accumulator starts at b3.  Output rows 0 and 1 land in
+// registers 0 and 1 of the half-0 lanes: o is valid there only (the lanes that use it).
+__device__ __forceinline__ void layer3(const uint16_t *Wbf, const float *sbias, const uint16_t *zero16,
+                                       const uint32_t *h2, int col, int hf, float &o0, float &o1)
+{
+    f32x16 acc = {};
+    acc[0] = sbias[128];
+    acc[1] = sbias[129];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const uint16_t *row = col < 2 ? Wbf + kOffW3 + 64 * col + 16 * kk + 8 * hf : zero16;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds8(row), pack4(h2 + 4 * kk), acc, 0, 0, 0);
+    }
+    o0 = acc[0];
+    o1 = acc[1];
 }
 
 // The 16 biases of output tile T of a hidden layer, for a lane of half hf, in slot order (units
@@ -259,19 +283,14 @@ __device__ __forceinline__ void layer2(const uint16_t *Wbf, const float *sbias, 
 }
 
 template <bool TRAIN>
-__device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint32_t *phi4, int lane,
-                                          Fwd &r)
+__device__ __forceinline__ void forward32(const uint16_t *Wbf, const float *sbias, const uint16_t *zero16,
+                                          const uint32_t *phi4, int lane, Fwd &r)
 {
     const int hf = lane >> 5, col = lane & 31;
     const bf16x8 bphi = pack4(phi4);
     layer1<TRAIN>(Wbf, sbias, bphi, col, hf, r.d1, r.h1);
     layer2<TRAIN>(Wbf, sbias, r.h1, col, hf, r.d2, r.h2);
-    float po0, po1;
-    layer3(Wbf, r.h2, hf, po0, po1);
-    // the two halves of a sample live in lanes l and l ^ 32; add them in a fixed order
-    const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
-    r.o[0] = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
-    r.o[1] = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
+    layer3(Wbf, sbias, zero16, r.h2, col, hf, r.o[0], r.o[1]);   // valid in the half-0 lanes
 }
 
 // ---------------------------------------------------------------- fit: affine base
@@ -740,11 +759,8 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_train(const FarArgs f)
             stage_row(h1s, col, hf, h1);
             layer2<true>(Wbf, sbias, h1, col, hf, d2, h2);
             stage_row(h2s, col, hf, h2);
-            float po0, po1;
-            layer3(Wbf, h2, hf, po0, po1);
-            const float q0 = __shfl_xor(po0, 32), q1 = __shfl_xor(po1, 32);
-            const float o0 = (hf == 0 ? po0 + q0 : q0 + po0) + sbias[128];
-            const float o1 = (hf == 0 ? po1 + q1 : q1 + po1) + sbias[129];
+            float o0, o1;
+            layer3_dot(Wbf, sbias, h2, hf, o0, o1);
             const float d30 = (o0 - t0) * inv_b, d31 = (o1 - t1) * inv_b;
             // dz2 = bf16(dh2 * silu'(z2)), dh2 = W3^T d3 as one 32x32x16 MFMA per output tile: d3 enters
             // as two bfloat16 terms hi + lo (equal to d3 within 2^-18 of it, far below the bfloat16
@@ -1078,6 +1094,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     __shared__ __attribute__((aligned(16))) uint16_t Wbf[kNParamsPad];
     __shared__ __attribute__((aligned(16))) float sbias[130];
     __shared__ float4 s_near[CAP];
+    __shared__ __attribute__((aligned(16))) uint32_t s_zero[4];
     __shared__ int s_cells[4];
     __shared__ uint32_t s_lost;
 
@@ -1096,6 +1113,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
     const float *bsrc = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(wsrc) + kTileBiasOff);
     for (int p = tid; p < kNParams; p += 256) Wbf[wslot(p)] = wsrc[p];
     for (int p = tid; p < 130; p += 256) sbias[p] = bsrc[p];
+    if (tid < 4) s_zero[tid] = 0u;
     if (tid == 0) {
         s_lost = 0u;
         // candidate cells: those overlapping the tile rectangle grown by r_near
@@ -1160,7 +1178,7 @@ __global__ void __launch_bounds__(256) k_surrogate(const FarArgs f, const CellAr
             uint32_t phi4[4];
             features8(u, phi4);
             Fwd fw;
-            forward32<false>(Wbf, sbias, phi4, lane, fw);
+            forward32<false>(Wbf, sbias, reinterpret_cast<const uint16_t *>(s_zero), phi4, lane, fw);
             o0 = fw.o[0];
             o1 = fw.o[1];
         }

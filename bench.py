@@ -87,7 +87,7 @@ def measured_traffic(workload_name: str, opts) -> float | None:
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or rec["workload"] != workload_name:
         return None
     cols, rows = (opts.block_cols or 1), (opts.block_rows or 4)
-    if f"{cols}x{rows}" != rec["block"] or (opts.fp32_run or 16) != rec["fp32_run"] \
+    if f"{cols}x{rows}" != rec["block"] or (opts.fp32_run or (8 if cols == 1 else 16)) != rec["fp32_run"] \
             or (opts.lens_tile or 256) != rec["lens_tile"]:
         return None
     return float(rec["hbm_bytes_per_launch"])
@@ -123,7 +123,8 @@ def mix_ceiling(rates: dict, opts) -> dict | None:
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     cols, rows = (opts.block_cols or 1), (opts.block_rows or 4)
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or f"{cols}x{rows}" != rec["block"] \
-            or (opts.fp32_run or 16) != rec["fp32_run"] or (opts.lens_tile or 256) != rec["lens_tile"]:
+            or (opts.fp32_run or (8 if cols == 1 else 16)) != rec["fp32_run"] \
+            or (opts.lens_tile or 256) != rec["lens_tile"]:
         return None
     k = rec["per_interaction"]
     rcp_cost = 14.0 / rates["mix_13fmac_1rcp"] - 13.0 / rates["fmac_f32"]

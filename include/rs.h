@@ -136,16 +136,18 @@ typedef struct {
 /*
  * Tuning and diagnostics for rs_shoot.  NULL, or a zero field, selects the
  * default.  Results depend on fp32_run (the length of the float32 runs before
- * each FP64 addition) and, when masses differ from 1, on whether the ray block
- * has one column or several (several columns fold the mass into the shared
- * differences, which rounds differently); lens_tile, map_window and the rows of
- * the block change speed, not values.
+ * each FP64 addition) and on whether the ray block has one column or several
+ * (one column: four rows share a reciprocal; several columns: pairs of rows
+ * share one and the mass is folded into the shared differences, which rounds
+ * differently); lens_tile, map_window and the rows of a several-column block
+ * change speed, not values.
  */
 typedef struct {
     int32_t block_cols;      /* rays per lane: block_cols grid columns x block_rows grid rows;  */
     int32_t block_rows;      /* 1x4, 2x2, 2x4, 4x2, 4x4 or 2x8 (0, 0 = default)               */
     int32_t lens_tile;       /* lenses staged in LDS per tile: 256 or 512 (default 256)        */
-    int32_t fp32_run;        /* lenses per float32 run: 8, 16 or 32 (default 16)               */
+    int32_t fp32_run;        /* lenses per float32 run: 8, 16 or 32 (default 8 with one column,
+                                16 with several)                                               */
     int32_t map_window;      /* side of the LDS-privatised map window: 16, 32 or 64; -1 = off */
     double *ray_y;           /* optional device output, 2 doubles per ray of the window        */
     int32_t *ray_pix;        /* optional device output, pixel p2*n1+p1 per ray, -1 = lost      */

@@ -45,9 +45,31 @@ __device__ __forceinline__ int pixel_of(double y1, double y2, const DirectArgs &
 // in [1, 2) with weight 1/x.
 constexpr double kRcpBiasComp = 1.0 + 6.41e-9;
 
-__device__ __forceinline__ float4 pad_lens()
+// Ray and lens coordinates enter the lens loop scaled by 2^-4.  The scaling is exact, so every
+// rounding is that of the unscaled arithmetic; it keeps the product of four squared distances (four
+// rows sharing one reciprocal) in the float32 range for lenses up to about 1e6 from the rays.  The
+// sums come out 2^4 times the deflection and are scaled back with the bias compensation.
+constexpr float kLoopScale = 0.0625f;
+constexpr double kLoopBack = kRcpBiasComp * 0.0625;
+
+// Lens i as the loop reads it: moved to the launch's time, coordinates scaled.
+__device__ __forceinline__ float4 loop_lens(const DirectArgs &a, int64_t i)
 {
-    return make_float4(kPadCoord, kPadCoord, 0.0f, 0.0f);
+    float4 l = moved_lens(a.lenses[i], a.vel, i, a.time);
+    l.x *= kLoopScale;
+    l.y *= kLoopScale;
+    return l;
+}
+
+// Zero-mass padding of the last lens tile: at lens 0's position, so that its squared distances are
+// ordinary numbers (products stay finite and its terms are exactly zero); a ray exactly there takes
+// the per-ray recomputation below, as a ray on lens 0 does anyway.
+__device__ __forceinline__ float4 pad_lens(const DirectArgs &a)
+{
+    float4 l = loop_lens(a, 0);
+    l.z = 0.0f;
+    l.w = 0.0f;
+    return l;
 }
 
 template <int LT>
@@ -59,18 +81,20 @@ struct TileSmem {
 };
 
 // Shoot one block of rays per lane with the whole workgroup: lane rays are the window-relative
-// columns c0 .. c0 + K1 - 1 and rows r0 .. r0 + K2 - 1 (r0 even); a ray counts only when its
-// column is below cmax and its row in [rmin, rmax).  `slot` selects the partial map the counts go
-// to.  Every thread of the workgroup must call it.
+// columns c0 .. c0 + K1 - 1 and rows r0 .. r0 + K2 - 1 (r0 a multiple of 4); a ray counts only when
+// its column is below cmax and its row in [rmin, rmax).  `slot` selects the partial map the counts
+// go to.  Every thread of the workgroup must call it.
 //
-// Rays share one reciprocal per pair of rows (r0 + 2p, r0 + 2p + 1): with ra and rb
-// the two squared distances to a lens, g = 1 / (ra rb) gives 1 / ra = g rb and 1 / rb = g ra
-// (simultaneous inversion), one v_rcp_f32 for two interactions.  Window rows are aligned so that
-// pairs are always (even, odd) grid rows, which keeps every ray's arithmetic independent of the
-// window, of the launch and of the rows per lane.  A lane whose sums end non-finite (a pair product of zero: a
-// ray on a lens) is recomputed with one reciprocal per ray, so a ray is lost exactly when its own
-// distance is zero.  A product above the float32 range (both rays more than 4e9 Einstein radii
-// from the lens) gives g = 0: such a lens deflects by less than 2.4e-10 m and is dropped.
+// Rays share reciprocals (simultaneous inversion).  With one column per lane, the four rows
+// r0 + 4p .. r0 + 4p + 3 share one: with q0 .. q3 their squared distances to a lens, g = 1 /
+// (q0 q1 q2 q3) gives 1 / q0 = g (q2 q3) q1 and so on, one v_rcp_f32 for four interactions; with
+// several columns per lane (the mass folded into the shared differences), pairs of rows share
+// one.  Window rows are aligned so that the groups are always grid rows 4p .. 4p + 3 (or pairs
+// within them), which keeps every ray's arithmetic independent of the window and of the launch.
+// A lane whose sums end non-finite (a product of zero: a ray on a lens) is recomputed with one
+// reciprocal per ray, so a ray is lost exactly when its own distance is zero.  A product above
+// the float32 range (all rays of the group more than about 1e6 Einstein radii from the lens)
+// gives g = 0: such a lens deflects by less than 1e-6 m and is dropped.
 template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
 __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int64_t r0, int64_t cmax, int64_t rmin,
                                            int64_t rmax, uint32_t slot, TileSmem<LT> &sm)
@@ -80,6 +104,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
     constexpr int PER = LT / kThreads;
     constexpr int R = K1 * K2;
     constexpr bool FOLD = K1 >= 2;  // fold m into shared differences when a lane has several columns
+    constexpr bool QUAD = K1 == 1 && K2 % 4 == 0;   // four rows per reciprocal
     auto &s_lens = sm.lens;
     auto &s_win = sm.win;
     auto &s_cand = sm.cand;
@@ -93,17 +118,17 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
     // their own coordinates, xj1 / xj2 per ray slot
     float x1[K1], x2[K2], xj1[JIT ? R : 1], xj2[JIT ? R : 1];
 #pragma unroll
-    for (int i = 0; i < K1; ++i) x1[i] = ray_coord(a.glo1, a.gt1, a.wlo1 + c0 + i);
+    for (int i = 0; i < K1; ++i) x1[i] = ray_coord(a.glo1, a.gt1, a.wlo1 + c0 + i) * kLoopScale;
 #pragma unroll
-    for (int b = 0; b < K2; ++b) x2[b] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + b);
+    for (int b = 0; b < K2; ++b) x2[b] = ray_coord(a.glo2, a.gt2, a.wlo2 + r0 + b) * kLoopScale;
     if constexpr (JIT) {
 #pragma unroll
         for (int i = 0; i < K1; ++i)
 #pragma unroll
             for (int b = 0; b < K2; ++b) {
                 const int64_t g1 = a.wlo1 + c0 + i, g2 = a.wlo2 + r0 + b, r = g2 * a.gn1 + g1;
-                xj1[i * K2 + b] = ray_coord(a.glo1, a.gt1, g1, jitter_u(a.jkey1, r));
-                xj2[i * K2 + b] = ray_coord(a.glo2, a.gt2, g2, jitter_u(a.jkey2, r));
+                xj1[i * K2 + b] = ray_coord(a.glo1, a.gt1, g1, jitter_u(a.jkey1, r)) * kLoopScale;
+                xj2[i * K2 + b] = ray_coord(a.glo2, a.gt2, g2, jitter_u(a.jkey2, r)) * kLoopScale;
             }
     }
 
@@ -121,7 +146,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             int64_t i = (int64_t)p * kThreads + tid;
-            reg[p] = i < a.n_lens ? moved_lens(a.lenses[i], a.vel, i, a.time) : pad_lens();
+            reg[p] = i < a.n_lens ? loop_lens(a, i) : pad_lens(a);
             s_lens[0][p * kThreads + tid] = reg[p];
         }
     }
@@ -134,7 +159,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 int64_t i = (t + 1) * LT + (int64_t)p * kThreads + tid;
-                reg[p] = i < a.n_lens ? moved_lens(a.lenses[i], a.vel, i, a.time) : pad_lens();
+                reg[p] = i < a.n_lens ? loop_lens(a, i) : pad_lens(a);
             }
         }
         const float4 *L = s_lens[buf];
@@ -143,7 +168,28 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
 #pragma unroll
             for (int j = 0; j < T; ++j) {
                 const float4 l = L[r + j];
-                if constexpr (JIT) {
+                if constexpr (JIT && QUAD) {
+                    // every ray has its own coordinates; the four rows still share the reciprocal
+#pragma unroll
+                    for (int k = 0; k < R; k += 4) {
+                        float dx[4], dy[4], q[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            dx[e] = xj1[k + e] - l.x;
+                            dy[e] = xj2[k + e] - l.y;
+                            q[e] = fmaf(dy[e], dy[e], dx[e] * dx[e]);
+                        }
+                        const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                        const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                        const float g01 = g * p23, g23 = g * p01;
+                        const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            s1[k + e] = j == 0 ? d[e] * dx[e] : fmaf(d[e], dx[e], s1[k + e]);
+                            s2[k + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[k + e]);
+                        }
+                    }
+                } else if constexpr (JIT) {
                     // every ray has its own coordinates; rows still pair up for the reciprocal
 #pragma unroll
                     for (int k = 0; k < R; k += 2) {
@@ -200,6 +246,29 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
                             }
                         }
                     }
+                } else if constexpr (QUAD) {
+                    // one column per lane, four rows per reciprocal: d = m / r^2 per ray, then
+                    // alpha += d (dx, dy)
+                    const float dx = x1[0] - l.x;
+                    const float dx2 = dx * dx;
+#pragma unroll
+                    for (int b = 0; b < K2; b += 4) {
+                        float dy[4], q[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            dy[e] = x2[b + e] - l.y;
+                            q[e] = fmaf(dy[e], dy[e], dx2);
+                        }
+                        const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                        const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                        const float g01 = g * p23, g23 = g * p01;
+                        const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            s1[b + e] = j == 0 ? d[e] * dx : fmaf(d[e], dx, s1[b + e]);
+                            s2[b + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[b + e]);
+                        }
+                    }
                 } else {
                     // one column per lane: d = m / r^2 per ray, then alpha += d (dx, dy)
                     const float dx = x1[0] - l.x;
@@ -238,8 +307,8 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
     }
 
     {
-        // A pair whose product left the finite range (a ray on a lens, or both rays within about
-        // 1e-19 of one) leaves a non-finite sum.  Redo this lane's rays with one reciprocal per
+        // A group whose product left the finite range (a ray on a lens, or the group's rays all
+        // very close to one) leaves a non-finite sum.  Redo this lane's rays with one reciprocal per
         // ray, in the same runs of T lenses, reading the lenses from global memory: every ray then
         // gets exactly the per-ray result, and only a ray on a lens stays non-finite.
         bool bad = false;
@@ -254,7 +323,7 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
                 for (int k = 0; k < R; ++k) { s1[k] = 0.0f; s2[k] = 0.0f; }
                 const int64_t e = min(r + (int64_t)T, a.n_lens);
                 for (int64_t li = r; li < e; ++li) {
-                    const float4 l = moved_lens(a.lenses[li], a.vel, li, a.time);
+                    const float4 l = loop_lens(a, li);
                     if constexpr (JIT) {
 #pragma unroll
                         for (int k = 0; k < R; ++k) {
@@ -298,11 +367,12 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
     // The hardware reciprocal is biased low: over all float32 mantissas, weighted as for
     // log-uniform arguments, its mean relative error is -6.41e-9.  Summed coherently over many
     // lenses this bias would dominate the float32 error of large deflections, so the FP64 sum
-    // is rescaled by the inverse factor (two FP64 multiplies per ray, no per-lens cost).
+    // is rescaled by the inverse factor (two FP64 multiplies per ray, no per-lens cost), together
+    // with the 2^-4 that undoes the coordinate scaling.
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        A1[k] *= kRcpBiasComp;
-        A2[k] *= kRcpBiasComp;
+        A1[k] *= kLoopBack;
+        A2[k] *= kLoopBack;
     }
 
     // Lens equation (eq. 6) and source pixel, FP64.
@@ -313,8 +383,8 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
         for (int b = 0; b < K2; ++b) {
             const int k = i * K2 + b;
             const bool ok = (c0 + i < cmax) && (r0 + b >= rmin) && (r0 + b < rmax);
-            const double y1 = a.lam1 * (double)(JIT ? xj1[k] : x1[i]) - A1[k];
-            const double y2 = a.lam2 * (double)(JIT ? xj2[k] : x2[b]) - A2[k];
+            const double y1 = a.lam1 * ((double)(JIT ? xj1[k] : x1[i]) * 16.0) - A1[k];
+            const double y2 = a.lam2 * ((double)(JIT ? xj2[k] : x2[b]) * 16.0) - A2[k];
             int p1 = 0, p2 = 0;
             const int kv = pixel_of(y1, y2, a, p1, p2);
             key[k] = ok ? kv : -2;
@@ -426,8 +496,8 @@ __global__ void __launch_bounds__(kThreads) k_direct(const DirectArgs a)
 // Persistent direct sum over the lane blocks of a list of culling cells (the cells a zoom
 // keeps).  Cell q of the list covers the caller's window columns [mx c1, (mx + 1) c1) and rows
 // [my c2, (my + 1) c2) (clipped to the window), i.e. rows shifted by rskip here; it is cut into
-// S = sx sy lane blocks of K1 columns x K2 rows starting at the even row at or below its first
-// row (so the row pairs are those of the plain launch), and block j of cell list[i] is lane
+// S = sx sy lane blocks of K1 columns x K2 rows starting at the multiple of 4 at or below its first
+// row (so the row groups are those of the plain launch), and block j of cell list[i] is lane
 // slot i S + j.  Workgroup g takes slots g 256 .. g 256 + 255, then g + grid, ...
 template <int K1, int K2, int T, int LT, bool JIT>
 __global__ void __launch_bounds__(kThreads) k_direct_cells(const DirectArgs a, const CellBlocks cb)
@@ -445,7 +515,7 @@ __global__ void __launch_bounds__(kThreads) k_direct_cells(const DirectArgs a, c
             const int64_t mx = cell % cb.ncx, my = cell / cb.ncx;
             c0 = mx * cb.c1 + (j % cb.sx) * K1;
             rmin = my * cb.c2 + a.rskip;
-            r0 = (rmin & ~int64_t(1)) + (j / cb.sx) * K2;
+            r0 = (rmin & ~int64_t(3)) + (j / cb.sx) * K2;
             cmax = min((mx + 1) * cb.c1, a.wn1);
             rmax = min((my + 1) * cb.c2 + a.rskip, a.wn2);
         }

@@ -38,9 +38,11 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 constexpr double kMaxCoord = 1.0e12;  // far below the position of the zero-mass padding lenses
 
-// Resolved tuning of one direct-sum launch.
+// Resolved tuning of one direct-sum launch.  T = 0 selects the float32 run length of the block
+// shape: 8 lenses with one column per lane (four rows share a reciprocal), 16 with several (pairs).
 struct Tune {
-    int K1 = 1, K2 = 4, T = 16, LT = 256, W = 64;
+    int K1 = 1, K2 = 4, T = 0, LT = 256, W = 64;
+    int run() const { return T ? T : (K1 == 1 ? 8 : 16); }
 };
 
 int resolve_opts(const rs_opts *o, Tune &t)
@@ -112,7 +114,7 @@ int validate_job(const rs_job *j)
 
 // Rows of the ray window as the direct-sum kernels see it: reciprocals are shared by pairs of
 // (even, odd) grid rows, so a window that starts on an odd row is widened by one masked row.
-int32_t row_skip(const rs_raygrid &g) { return g.win_n[1] > 0 ? (int32_t)(g.win_lo[1] & 1) : 0; }
+int32_t row_skip(const rs_raygrid &g) { return g.win_n[1] > 0 ? (int32_t)(g.win_lo[1] & 3) : 0; }
 int64_t kernel_rows(const rs_raygrid &g) { return g.win_n[1] + row_skip(g); }
 
 int64_t partial_stride(const rs_job *j)
@@ -285,7 +287,7 @@ int prepare_batch(const rs_job *jobs, int32_t n_jobs, void *workspace, size_t ws
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return dev_fail(e, "device query");
-    const int occ = rs::batched_occupancy(t.K1, t.K2, t.T, t.LT);
+    const int occ = rs::batched_occupancy(t.K1, t.K2, t.run(), t.LT);
     if (occ <= 0) return fail(RS_EINTERNAL, "no occupancy for the batched kernel");
 
     {
@@ -318,14 +320,14 @@ int run_batch(const PreparedBatch &pb, const Tune &t, void *workspace, hipStream
     if (pb.args.n_items == 0) return RS_OK;
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = rs::launch_fill_u32(pb.args.queue, 1, 0u, s);
-        if (e == hipSuccess) e = rs::launch_batched(pb.args, t.K1, t.K2, t.T, t.LT, pb.grid, s);
+        if (e == hipSuccess) e = rs::launch_batched(pb.args, t.K1, t.K2, t.run(), t.LT, pb.grid, s);
         return e;
     };
     if (!use_graph || s == nullptr) {
         const hipError_t e = enqueue();
         return e == hipSuccess ? RS_OK : dev_fail(e, "batched launch");
     }
-    const GraphKey key{workspace, pb.device, t.K1, t.K2, t.T, t.LT, t.W, pb.grid, pb.args.n_jobs, pb.args.n_items};
+    const GraphKey key{workspace, pb.device, t.K1, t.K2, t.run(), t.LT, t.W, pb.grid, pb.args.n_jobs, pb.args.n_items};
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -512,7 +514,7 @@ int shoot_with_partials(const rs_job *job, const Tune &t, uint32_t *part, hipStr
     const rs::DirectArgs a = make_args(job, t, part, pstride, opts);
     hipError_t e = rs::launch_zero(part, rs::kPartials * pstride, s);
     if (e != hipSuccess) return dev_fail(e, "zero partial maps");
-    e = rs::launch_direct(a, t.K1, t.K2, t.T, t.LT, tile_count(job, t), s);
+    e = rs::launch_direct(a, t.K1, t.K2, t.run(), t.LT, tile_count(job, t), s);
     if (e != hipSuccess) return dev_fail(e, "direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");
@@ -668,9 +670,9 @@ int zoom_layout(const rs_job *job, const rs_zoom *z, const Tune &t, ZoomLayout &
     L.cells = L.ncx * L.ncy;
     if (L.cells > (int64_t(1) << 30)) return fail(RS_ERANGE, "more than 2^30 culling cells; use larger cells");
     L.sx = (c1 + t.K1 - 1) / t.K1;
-    // lane blocks start at the even kernel row at or below a cell's first row: one more row to
-    // cover when cells can start on an odd kernel row
-    const int64_t span2 = c2 + ((c2 % 2 != 0 || row_skip(g) != 0) ? 1 : 0);
+    // lane blocks start at the kernel row at or below a cell's first row that is a multiple of 4:
+    // up to three more rows to cover when cells can start elsewhere
+    const int64_t span2 = c2 + ((c2 % 4 != 0 || row_skip(g) != 0) ? 3 : 0);
     L.S = L.sx * ((span2 + t.K2 - 1) / t.K2);
     if ((uint64_t)L.cells * (uint64_t)L.S * (uint64_t)(t.K1 * t.K2) >= (uint64_t(1) << 40))
         return fail(RS_ERANGE, "too many ray slots");
@@ -1051,7 +1053,7 @@ int rs_shoot_zoom(const rs_job *job, const rs_zoom *zoom, void *workspace, size_
     if (e != hipSuccess) return dev_fail(e, "zero partial maps");
     e = rs::launch_zoom_mark(z, s);
     if (e != hipSuccess) return dev_fail(e, "zoom culling launch");
-    e = rs::launch_direct_cells(a, t.K1, t.K2, t.T, t.LT, cb, max_groups, s);
+    e = rs::launch_direct_cells(a, t.K1, t.K2, t.run(), t.LT, cb, max_groups, s);
     if (e != hipSuccess) return dev_fail(e, "zoom direct-sum launch");
     e = rs::launch_reduce(part, bins, pstride, job->counts, s);
     if (e != hipSuccess) return dev_fail(e, "map reduce launch");

@@ -23,11 +23,12 @@ struct DirectArgs {
     int64_t n_lens;
     double glo1, glo2;      // grid lower corner
     double gt1, gt2;        // grid cell size (hi - lo) / n, computed on the host in FP64
-    int64_t wlo1, wlo2;     // ray window origin (grid indices); wlo2 is even (see rskip)
+    int64_t wlo1, wlo2;     // ray window origin (grid indices); wlo2 is a multiple of 4 (see rskip)
     int64_t wn1, wn2;       // ray window size
-    int32_t rskip;          // 1 when the caller's window starts on an odd grid row: the window
-                            // here then starts one row earlier and its first row is masked, so
-                            // rows pair up as (even, odd) grid rows in every launch shape
+    int32_t rskip;          // 0-3: the caller's window start row modulo 4; the window here then
+                            // starts that many rows earlier and those rows are masked, so the
+                            // rows that share a reciprocal (grid rows 4k..4k+3, or pairs of them)
+                            // are the same in every launch shape
     int32_t tiles_x;        // ceil(wn1 / (64 K1))
     double lam1, lam2;      // (1 - gamma) - kappa_c, (1 + gamma) - kappa_c
     double mlo1, mlo2;      // map lower corner

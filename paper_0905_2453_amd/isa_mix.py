@@ -40,7 +40,8 @@ def _asm(path: str) -> str:
     return open(out).read()
 
 
-def count(block=(1, 4), T=16, LT=256) -> dict:
+def count(block=(1, 4), T=0, LT=256) -> dict:
+    T = T or (8 if block[0] == 1 else 16)
     src = os.path.join(B.CSRC, "direct.hip")
     lines = _asm(src).split("\n")
     sym = f"k_directILi{block[0]}ELi{block[1]}ELi{T}ELi{LT}ELb0ELb0E"

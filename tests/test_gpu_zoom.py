@@ -101,7 +101,7 @@ def test_zoom_equals_fine_grid_bench_configuration():
 @pytest.mark.parametrize("block,jitter,cell", [((2, 4), None, (5, 7)), ((1, 4), 29, (0, 0)), ((4, 2), 3, (3, 9))])
 def test_zoom_odd_window_blocks_and_jitter(block, jitter, cell):
     # a window starting on an odd row and column, several lane shapes, jittered rays and odd cell
-    # sizes: the zoom still adds exactly the plain shoot's counts (row pairs stay aligned)
+    # sizes: the zoom still adds exactly the plain shoot's counts (rows sharing a reciprocal stay aligned)
     torch, P = _env()
     w = synth.workload_paper(n_lens=20000, grid=4096)
     o = P.Opts()

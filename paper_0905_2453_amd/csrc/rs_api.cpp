@@ -112,8 +112,9 @@ int validate_job(const rs_job *j)
     return RS_OK;
 }
 
-// Rows of the ray window as the direct-sum kernels see it: reciprocals are shared by pairs of
-// (even, odd) grid rows, so a window that starts on an odd row is widened by one masked row.
+// Rows of the ray window as the direct-sum kernels see it: reciprocals are shared by grid rows
+// 4k..4k+3 (or pairs of them), so a window whose first row is not a multiple of 4 is widened by up
+// to three masked rows.
 int32_t row_skip(const rs_raygrid &g) { return g.win_n[1] > 0 ? (int32_t)(g.win_lo[1] & 3) : 0; }
 int64_t kernel_rows(const rs_raygrid &g) { return g.win_n[1] + row_skip(g); }
 

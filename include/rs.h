@@ -147,7 +147,8 @@ typedef struct {
     int32_t block_rows;      /* 1x4, 2x2, 2x4, 4x2, 4x4 or 2x8 (0, 0 = default)               */
     int32_t lens_tile;       /* lenses staged in LDS per tile: 256 or 512 (default 256)        */
     int32_t fp32_run;        /* lenses per float32 run: 8, 16 or 32 (default 8 with one column,
-                                16 with several)                                               */
+                                16 with several); one-column blocks add four runs in float32
+                                before each FP64 addition, several-column blocks add each run  */
     int32_t map_window;      /* side of the LDS-privatised map window: 16, 32 or 64; -1 = off */
     double *ray_y;           /* optional device output, 2 doubles per ray of the window        */
     int32_t *ray_pix;        /* optional device output, pixel p2*n1+p1 per ray, -1 = lost      */

@@ -52,6 +52,11 @@ constexpr double kRcpBiasComp = 1.0 + 6.41e-9;
 constexpr float kLoopScale = 0.0625f;
 constexpr double kLoopBack = kRcpBiasComp * 0.0625;
 
+// One-column blocks add kQuadRuns consecutive float32 runs in float32 before the FP64 addition:
+// one float32 add per run instead of a conversion and an FP64 add, at an error between that of
+// single runs and of one run kQuadRuns times as long.
+constexpr int kQuadRuns = 4;
+
 // Lens i as the loop reads it: moved to the launch's time, coordinates scaled.
 __device__ __forceinline__ float4 loop_lens(const DirectArgs &a, int64_t i)
 {
@@ -99,12 +104,13 @@ template <int K1, int K2, int T, int LT, bool DUMP, bool JIT>
 __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int64_t r0, int64_t cmax, int64_t rmin,
                                            int64_t rmax, uint32_t slot, TileSmem<LT> &sm)
 {
-    static_assert(LT % kThreads == 0 && LT % T == 0, "tile shape");
     static_assert(K2 % 2 == 0, "rows pair up");
     constexpr int PER = LT / kThreads;
     constexpr int R = K1 * K2;
     constexpr bool FOLD = K1 >= 2;  // fold m into shared differences when a lane has several columns
     constexpr bool QUAD = K1 == 1 && K2 % 4 == 0;   // four rows per reciprocal
+    constexpr int G = QUAD ? kQuadRuns : 1;         // float32 runs per FP64 addition
+    static_assert(LT % kThreads == 0 && LT % (T * G) == 0, "tile shape");
     auto &s_lens = sm.lens;
     auto &s_win = sm.win;
     auto &s_cand = sm.cand;
@@ -163,140 +169,149 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
             }
         }
         const float4 *L = s_lens[buf];
-        for (int r = 0; r < LT; r += T) {
-            float s1[R], s2[R];
+        for (int r = 0; r < LT; r += T * G) {
+            float m1[R], m2[R];
 #pragma unroll
-            for (int j = 0; j < T; ++j) {
-                const float4 l = L[r + j];
-                if constexpr (JIT && QUAD) {
-                    // every ray has its own coordinates; the four rows still share the reciprocal
+            for (int h = 0; h < G; ++h) {
+                float s1[R], s2[R];
 #pragma unroll
-                    for (int k = 0; k < R; k += 4) {
-                        float dx[4], dy[4], q[4];
+                for (int j = 0; j < T; ++j) {
+                    const float4 l = L[r + h * T + j];
+                    if constexpr (JIT && QUAD) {
+                        // every ray has its own coordinates; the four rows still share the reciprocal
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            dx[e] = xj1[k + e] - l.x;
-                            dy[e] = xj2[k + e] - l.y;
-                            q[e] = fmaf(dy[e], dy[e], dx[e] * dx[e]);
+                        for (int k = 0; k < R; k += 4) {
+                            float dx[4], dy[4], q[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                dx[e] = xj1[k + e] - l.x;
+                                dy[e] = xj2[k + e] - l.y;
+                                q[e] = fmaf(dy[e], dy[e], dx[e] * dx[e]);
+                            }
+                            const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                            const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                            const float g01 = g * p23, g23 = g * p01;
+                            const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                s1[k + e] = j == 0 ? d[e] * dx[e] : fmaf(d[e], dx[e], s1[k + e]);
+                                s2[k + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[k + e]);
+                            }
                         }
-                        const float p01 = q[0] * q[1], p23 = q[2] * q[3];
-                        const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
-                        const float g01 = g * p23, g23 = g * p01;
-                        const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+                    } else if constexpr (JIT) {
+                        // every ray has its own coordinates; rows still pair up for the reciprocal
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            s1[k + e] = j == 0 ? d[e] * dx[e] : fmaf(d[e], dx[e], s1[k + e]);
-                            s2[k + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[k + e]);
+                        for (int k = 0; k < R; k += 2) {
+                            const float dxa = xj1[k] - l.x, dya = xj2[k] - l.y;
+                            const float dxb = xj1[k + 1] - l.x, dyb = xj2[k + 1] - l.y;
+                            const float ra = fmaf(dya, dya, dxa * dxa), rb = fmaf(dyb, dyb, dxb * dxb);
+                            const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
+                            const float da = g * rb, db = g * ra;
+                            if (j == 0) {
+                                s1[k] = da * dxa;
+                                s2[k] = da * dya;
+                                s1[k + 1] = db * dxb;
+                                s2[k + 1] = db * dyb;
+                            } else {
+                                s1[k] = fmaf(da, dxa, s1[k]);
+                                s2[k] = fmaf(da, dya, s2[k]);
+                                s1[k + 1] = fmaf(db, dxb, s1[k + 1]);
+                                s2[k + 1] = fmaf(db, dyb, s2[k + 1]);
+                            }
                         }
-                    }
-                } else if constexpr (JIT) {
-                    // every ray has its own coordinates; rows still pair up for the reciprocal
+                    } else if constexpr (FOLD) {
+                        // shared per column: x1 - x1_i, its square and m (x1 - x1_i);
+                        // per row: x2 - x2_i and m (x2 - x2_i)
+                        float dx[K1], dx2[K1], mdx[K1], dy[K2], mdy[K2];
 #pragma unroll
-                    for (int k = 0; k < R; k += 2) {
-                        const float dxa = xj1[k] - l.x, dya = xj2[k] - l.y;
-                        const float dxb = xj1[k + 1] - l.x, dyb = xj2[k + 1] - l.y;
-                        const float ra = fmaf(dya, dya, dxa * dxa), rb = fmaf(dyb, dyb, dxb * dxb);
-                        const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
-                        const float da = g * rb, db = g * ra;
-                        if (j == 0) {
-                            s1[k] = da * dxa;
-                            s2[k] = da * dya;
-                            s1[k + 1] = db * dxb;
-                            s2[k + 1] = db * dyb;
-                        } else {
-                            s1[k] = fmaf(da, dxa, s1[k]);
-                            s2[k] = fmaf(da, dya, s2[k]);
-                            s1[k + 1] = fmaf(db, dxb, s1[k + 1]);
-                            s2[k + 1] = fmaf(db, dyb, s2[k + 1]);
+                        for (int i = 0; i < K1; ++i) {
+                            dx[i] = x1[i] - l.x;
+                            dx2[i] = dx[i] * dx[i];
+                            mdx[i] = l.z * dx[i];
                         }
-                    }
-                } else if constexpr (FOLD) {
-                    // shared per column: x1 - x1_i, its square and m (x1 - x1_i);
-                    // per row: x2 - x2_i and m (x2 - x2_i)
-                    float dx[K1], dx2[K1], mdx[K1], dy[K2], mdy[K2];
 #pragma unroll
-                    for (int i = 0; i < K1; ++i) {
-                        dx[i] = x1[i] - l.x;
-                        dx2[i] = dx[i] * dx[i];
-                        mdx[i] = l.z * dx[i];
-                    }
+                        for (int b = 0; b < K2; ++b) {
+                            dy[b] = x2[b] - l.y;
+                            mdy[b] = l.z * dy[b];
+                        }
 #pragma unroll
-                    for (int b = 0; b < K2; ++b) {
-                        dy[b] = x2[b] - l.y;
-                        mdy[b] = l.z * dy[b];
-                    }
+                        for (int i = 0; i < K1; ++i) {
 #pragma unroll
-                    for (int i = 0; i < K1; ++i) {
+                            for (int b = 0; b < K2; b += 2) {
+                                const int k = i * K2 + b;
+                                const float ra = fmaf(dy[b], dy[b], dx2[i]), rb = fmaf(dy[b + 1], dy[b + 1], dx2[i]);
+                                const float g = __builtin_amdgcn_rcpf(ra * rb);
+                                const float qa = g * rb, qb = g * ra;
+                                if (j == 0) {
+                                    s1[k] = qa * mdx[i];
+                                    s2[k] = qa * mdy[b];
+                                    s1[k + 1] = qb * mdx[i];
+                                    s2[k + 1] = qb * mdy[b + 1];
+                                } else {
+                                    s1[k] = fmaf(qa, mdx[i], s1[k]);
+                                    s2[k] = fmaf(qa, mdy[b], s2[k]);
+                                    s1[k + 1] = fmaf(qb, mdx[i], s1[k + 1]);
+                                    s2[k + 1] = fmaf(qb, mdy[b + 1], s2[k + 1]);
+                                }
+                            }
+                        }
+                    } else if constexpr (QUAD) {
+                        // one column per lane, four rows per reciprocal: d = m / r^2 per ray, then
+                        // alpha += d (dx, dy)
+                        const float dx = x1[0] - l.x;
+                        const float dx2 = dx * dx;
+#pragma unroll
+                        for (int b = 0; b < K2; b += 4) {
+                            float dy[4], q[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                dy[e] = x2[b + e] - l.y;
+                                q[e] = fmaf(dy[e], dy[e], dx2);
+                            }
+                            const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                            const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                            const float g01 = g * p23, g23 = g * p01;
+                            const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                s1[b + e] = j == 0 ? d[e] * dx : fmaf(d[e], dx, s1[b + e]);
+                                s2[b + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[b + e]);
+                            }
+                        }
+                    } else {
+                        // one column per lane: d = m / r^2 per ray, then alpha += d (dx, dy)
+                        const float dx = x1[0] - l.x;
+                        const float dx2 = dx * dx;
 #pragma unroll
                         for (int b = 0; b < K2; b += 2) {
-                            const int k = i * K2 + b;
-                            const float ra = fmaf(dy[b], dy[b], dx2[i]), rb = fmaf(dy[b + 1], dy[b + 1], dx2[i]);
-                            const float g = __builtin_amdgcn_rcpf(ra * rb);
-                            const float qa = g * rb, qb = g * ra;
+                            const float dya = x2[b] - l.y, dyb = x2[b + 1] - l.y;
+                            const float ra = fmaf(dya, dya, dx2), rb = fmaf(dyb, dyb, dx2);
+                            const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
+                            const float da = g * rb, db = g * ra;
                             if (j == 0) {
-                                s1[k] = qa * mdx[i];
-                                s2[k] = qa * mdy[b];
-                                s1[k + 1] = qb * mdx[i];
-                                s2[k + 1] = qb * mdy[b + 1];
+                                s1[b] = da * dx;
+                                s2[b] = da * dya;
+                                s1[b + 1] = db * dx;
+                                s2[b + 1] = db * dyb;
                             } else {
-                                s1[k] = fmaf(qa, mdx[i], s1[k]);
-                                s2[k] = fmaf(qa, mdy[b], s2[k]);
-                                s1[k + 1] = fmaf(qb, mdx[i], s1[k + 1]);
-                                s2[k + 1] = fmaf(qb, mdy[b + 1], s2[k + 1]);
+                                s1[b] = fmaf(da, dx, s1[b]);
+                                s2[b] = fmaf(da, dya, s2[b]);
+                                s1[b + 1] = fmaf(db, dx, s1[b + 1]);
+                                s2[b + 1] = fmaf(db, dyb, s2[b + 1]);
                             }
                         }
                     }
-                } else if constexpr (QUAD) {
-                    // one column per lane, four rows per reciprocal: d = m / r^2 per ray, then
-                    // alpha += d (dx, dy)
-                    const float dx = x1[0] - l.x;
-                    const float dx2 = dx * dx;
+                }
 #pragma unroll
-                    for (int b = 0; b < K2; b += 4) {
-                        float dy[4], q[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            dy[e] = x2[b + e] - l.y;
-                            q[e] = fmaf(dy[e], dy[e], dx2);
-                        }
-                        const float p01 = q[0] * q[1], p23 = q[2] * q[3];
-                        const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
-                        const float g01 = g * p23, g23 = g * p01;
-                        const float d[4] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            s1[b + e] = j == 0 ? d[e] * dx : fmaf(d[e], dx, s1[b + e]);
-                            s2[b + e] = j == 0 ? d[e] * dy[e] : fmaf(d[e], dy[e], s2[b + e]);
-                        }
-                    }
-                } else {
-                    // one column per lane: d = m / r^2 per ray, then alpha += d (dx, dy)
-                    const float dx = x1[0] - l.x;
-                    const float dx2 = dx * dx;
-#pragma unroll
-                    for (int b = 0; b < K2; b += 2) {
-                        const float dya = x2[b] - l.y, dyb = x2[b + 1] - l.y;
-                        const float ra = fmaf(dya, dya, dx2), rb = fmaf(dyb, dyb, dx2);
-                        const float g = l.z * __builtin_amdgcn_rcpf(ra * rb);
-                        const float da = g * rb, db = g * ra;
-                        if (j == 0) {
-                            s1[b] = da * dx;
-                            s2[b] = da * dya;
-                            s1[b + 1] = db * dx;
-                            s2[b + 1] = db * dyb;
-                        } else {
-                            s1[b] = fmaf(da, dx, s1[b]);
-                            s2[b] = fmaf(da, dya, s2[b]);
-                            s1[b + 1] = fmaf(db, dx, s1[b + 1]);
-                            s2[b + 1] = fmaf(db, dyb, s2[b + 1]);
-                        }
-                    }
+                for (int k = 0; k < R; ++k) {
+                    m1[k] = h == 0 ? s1[k] : m1[k] + s1[k];
+                    m2[k] = h == 0 ? s2[k] : m2[k] + s2[k];
                 }
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                A1[k] += (double)s1[k];
-                A2[k] += (double)s2[k];
+                A1[k] += (double)m1[k];
+                A2[k] += (double)m2[k];
             }
         }
         if (more) {
@@ -309,14 +324,16 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
     {
         // A group whose product left the finite range (a ray on a lens, or the group's rays all
         // very close to one) leaves a non-finite sum.  Redo this lane's rays with one reciprocal per
-        // ray, in the same runs of T lenses, reading the lenses from global memory: every ray then
-        // gets exactly the per-ray result, and only a ray on a lens stays non-finite.
+        // ray, in the same runs of T lenses and groups of G runs, reading the lenses from global
+        // memory: every ray then gets exactly the per-ray result, and only a ray on a lens stays
+        // non-finite.
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < R; ++k) bad = bad || !__builtin_isfinite(A1[k] + A2[k]);
         if (bad) {
 #pragma unroll
             for (int k = 0; k < R; ++k) { A1[k] = 0.0; A2[k] = 0.0; }
+            float m1[R], m2[R];
             for (int64_t r = 0; r < a.n_lens; r += T) {
                 float s1[R], s2[R];
 #pragma unroll
@@ -355,10 +372,19 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
                         }
                     }
                 }
+                // runs are grouped as in the lens loop: G runs added in float32, then in FP64
+                const bool first = (r / T) % G == 0, last = (r / T) % G == G - 1 || e == a.n_lens;
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
-                    A1[k] += (double)s1[k];
-                    A2[k] += (double)s2[k];
+                    m1[k] = first ? s1[k] : m1[k] + s1[k];
+                    m2[k] = first ? s2[k] : m2[k] + s2[k];
+                }
+                if (last) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        A1[k] += (double)m1[k];
+                        A2[k] += (double)m2[k];
+                    }
                 }
             }
         }

@@ -2,8 +2,8 @@
 
 Compiles csrc/direct.hip to device assembly with the library's flags, finds the kernel
 k_direct<K1, K2, T, LT, no dump, cell centres>, takes its lens loop (the basic block that holds
-the reciprocals: one float32 run of T lenses for the lane's K1 K2 rays) and counts its
-instructions by class, per ray-lens interaction.  With the issue rates of rs_probe_issue_rate
+the reciprocals: the float32 runs between two FP64 additions for the lane's K1 K2 rays) and
+counts its instructions by class, per ray-lens interaction.  With the issue rates of rs_probe_issue_rate
 this gives the loop's instruction-mix ceiling.
 
     python -m paper_0905_2453_amd.isa_mix [--block 1x4] [--out profiles/k_direct_isa_mix.json]
@@ -58,9 +58,10 @@ def count(block=(1, 4), T=0, LT=256) -> dict:
         t = l.strip()
         if cur and t and not t.startswith((";", ".")):
             blocks[cur].append(t.split()[0])
-    # the lens loop: the block with the most reciprocals
+    # the lens loop: the block with the most reciprocals; one reciprocal serves four rays in
+    # one-column blocks, two in several-column ones
     name, ins = max(blocks.items(), key=lambda kv: sum(1 for x in kv[1] if x.startswith("v_rcp_f32")))
-    inter = T * block[0] * block[1]
+    inter = sum(1 for x in ins if x.startswith("v_rcp_f32")) * (4 if block[0] == 1 else 2)
     hist = collections.Counter(ins)
     per = {k: sum(v for op, v in hist.items() if rx.match(op)) / inter for k, rx in CLASSES.items()}
     per["valu_total"] = sum(v for op, v in hist.items() if op.startswith("v_")) / inter

@@ -402,7 +402,8 @@ __global__ void __launch_bounds__(256) k_ff_affine(const FarArgs f)
 // Samples come in groups g of 256: sample 64 (4 g + k) + i, k = 0..3, i = 0..63; thread i of wave w
 // takes k = 0..3 of group 4 part + w.
 // Direct sum over every lens with the near ones swapped for zero-mass padding, float32 runs
-// of 16 lenses, FP64 combination; writes the residual after the affine base (unnormalised).
+// of 16 lenses added four at a time in float32, then in FP64; writes the residual after the
+// affine base (unnormalised).
 // The four samples of a thread share one reciprocal per lens (simultaneous inversion of the
 // product of their four squared distances: a far lens is at least r_near from every sample, so no
 // product is zero).  Coordinates are staged scaled by 2^-4 (exact), which keeps that product in the
@@ -428,7 +429,8 @@ constexpr float kSamplePad = 1.0e9f;
 template <bool GRID>
 __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
 {
-    constexpr int LT = 256, T = 16, S = 4;
+    constexpr int LT = 256, T = 16, G = 4, S = 4;   // G runs of T lenses are added in float32, then in FP64
+    static_assert(LT % (T * G) == 0, "tile shape");
     __shared__ float4 s_lens[2][LT];
     const uint32_t tile = blockIdx.x / (uint32_t)parts, part = blockIdx.x % (uint32_t)parts;
     double lo[2], hi[2], c[2], hw[2];
@@ -460,34 +462,43 @@ __global__ void __launch_bounds__(256) k_ff_samples(const FarArgs f, int parts)
         const bool more = t + 1 < n_tiles;
         if (more) reg = fetch((t + 1) * LT + tid);
         const float4 *L = s_lens[buf];
-        for (int r = 0; r < LT; r += T) {
-            float s1[S], s2[S];
+        for (int r = 0; r < LT; r += T * G) {
+            float m1[S], m2[S];
 #pragma unroll
-            for (int j = 0; j < T; ++j) {
-                const float4 l = L[r + j];
-                // GRID: the four samples share px[0]
-                const float dxs = px[0] - l.x, dxs2 = dxs * dxs;
-                float dx[S], dy[S], q[S];
+            for (int h = 0; h < G; ++h) {
+                float s1[S], s2[S];
 #pragma unroll
-                for (int k = 0; k < S; ++k) {
-                    dx[k] = GRID ? dxs : px[k] - l.x;
-                    dy[k] = py[k] - l.y;
-                    q[k] = fmaf(dy[k], dy[k], GRID ? dxs2 : dx[k] * dx[k]);
+                for (int j = 0; j < T; ++j) {
+                    const float4 l = L[r + h * T + j];
+                    // GRID: the four samples share px[0]
+                    const float dxs = px[0] - l.x, dxs2 = dxs * dxs;
+                    float dx[S], dy[S], q[S];
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        dx[k] = GRID ? dxs : px[k] - l.x;
+                        dy[k] = py[k] - l.y;
+                        q[k] = fmaf(dy[k], dy[k], GRID ? dxs2 : dx[k] * dx[k]);
+                    }
+                    const float p01 = q[0] * q[1], p23 = q[2] * q[3];
+                    const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
+                    const float g01 = g * p23, g23 = g * p01;
+                    const float d[S] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        s1[k] = j == 0 ? d[k] * dx[k] : fmaf(d[k], dx[k], s1[k]);
+                        s2[k] = j == 0 ? d[k] * dy[k] : fmaf(d[k], dy[k], s2[k]);
+                    }
                 }
-                const float p01 = q[0] * q[1], p23 = q[2] * q[3];
-                const float g = l.z * __builtin_amdgcn_rcpf(p01 * p23);
-                const float g01 = g * p23, g23 = g * p01;
-                const float d[S] = {g01 * q[1], g01 * q[0], g23 * q[3], g23 * q[2]};
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
-                    s1[k] = j == 0 ? d[k] * dx[k] : fmaf(d[k], dx[k], s1[k]);
-                    s2[k] = j == 0 ? d[k] * dy[k] : fmaf(d[k], dy[k], s2[k]);
+                    m1[k] = h == 0 ? s1[k] : m1[k] + s1[k];
+                    m2[k] = h == 0 ? s2[k] : m2[k] + s2[k];
                 }
             }
 #pragma unroll
             for (int k = 0; k < S; ++k) {
-                A1[k] += (double)s1[k];
-                A2[k] += (double)s2[k];
+                A1[k] += (double)m1[k];
+                A2[k] += (double)m2[k];
             }
         }
         if (more) s_lens[buf ^ 1][tid] = reg;

@@ -20,11 +20,16 @@ _lib = None
 
 
 def lib():
-    """The loaded librs.so (raises RuntimeError when it has not been built)."""
+    """The loaded librs.so (raises RuntimeError when it has not been built).
+
+    torch is imported first so that librs binds to the HIP runtime torch has loaded: the streams
+    and device pointers it hands over belong to that runtime, and a second runtime loaded ahead
+    of it would not see the device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0905_2453_amd.build.build()")
+        import torch  # noqa: F401
         _lib = _abi.bind(ctypes.CDLL(LIB_PATH))
     return _lib
 

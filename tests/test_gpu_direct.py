@@ -242,6 +242,42 @@ def test_ray_on_lens_is_lost_on_gpu(row, block):
     assert np.array_equal(rp.astype(np.int64), p_o)
 
 
+@pytest.mark.parametrize("block", [(1, 4), (2, 4)])
+def test_ray_on_lens_among_many_lenses(block):
+    # 1000 lenses (31 full groups of 32 and a partial one), one of them exactly on a grid ray: the
+    # lane holding that ray is redone with one reciprocal per ray in the same runs and groups; the
+    # ray is lost, every other ray lands where the oracle puts it, within the float32 bound
+    P = _P()
+    rng = np.random.default_rng(21)
+    n = 32
+    xs = oracle.axis(-1.0, 1.0, n)
+    L = np.zeros((1000, 4), dtype=np.float32)
+    r = 30.0 * np.sqrt(rng.random(1000))
+    t = 2 * np.pi * rng.random(1000)
+    L[:, 0], L[:, 1], L[:, 2] = r * np.cos(t), r * np.sin(t), 0.1 + 0.9 * rng.random(1000)
+    L[517, 0], L[517, 1] = xs[5], xs[13]
+    w = synth.Workload("hit-many", L, 0.0, 0.1, (-1.0, -1.0), (1.0, 1.0), (n, n), (-20.0, -20.0), (20.0, 20.0),
+                       (64, 64))
+    o = P.Opts()
+    o.block_cols, o.block_rows = block
+    counts, lost, ry, rp = run(w, opts=o, dump=True)
+    y_o, p_o = oracle.trace(w, np.arange(n * n))
+    hit = 13 * n + 5
+    share = (12, 14, 15) if block[0] == 1 else (12,)
+    assert rp[hit] == -1 and p_o[hit] == -1 and all(p_o[k * n + 5] >= 0 for k in share)
+    assert np.array_equal(rp.astype(np.int64), p_o)
+    ok = np.isfinite(y_o).all(1)
+    assert ok.sum() == n * n - 1
+    x = np.stack(np.meshgrid(xs, xs), -1).reshape(-1, 2).astype(np.float64)
+    Ld = L.astype(np.float64)
+    s = np.zeros(n * n)
+    for rec in Ld:
+        with np.errstate(divide="ignore"):
+            s += rec[2] / np.hypot(x[:, 0] - rec[0], x[:, 1] - rec[1])
+    err = np.abs(ry[ok] - y_o[ok]).max(1)
+    assert np.all(err <= (8 + 16) * U32 * s[ok] + 1e-12), float((err / s[ok]).max() / U32)
+
+
 def test_odd_window_dump_matches_oracle():
     # a window starting on an odd row and column, ragged in both axes: per-ray dumps keep the
     # caller's window indexing and every ray matches the oracle

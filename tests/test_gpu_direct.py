@@ -123,7 +123,7 @@ def test_deterministic_and_tiling_invariant():
         assert np.array_equal(got[2], want[2]) and np.array_equal(got[3], want[3])
 
 
-@pytest.mark.parametrize("T", [8, 32])
+@pytest.mark.parametrize("T", [8, 16, 32])
 def test_fp32_run_length_variants_within_tolerance(T):
     P = _P()
     w = synth.workload_small(seed=3)

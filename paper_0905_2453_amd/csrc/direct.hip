@@ -169,7 +169,11 @@ __device__ __forceinline__ void shoot_rays(const DirectArgs &a, int64_t c0, int6
             }
         }
         const float4 *L = s_lens[buf];
-        for (int r = 0; r < LT; r += T * G) {
+        // the last tile stops after the group of runs that holds the last lens: a group of
+        // padding alone would add exact zeros
+        const int64_t rest = a.n_lens - t * LT;
+        const int lim = rest >= LT ? LT : (int)((rest + T * G - 1) / (T * G)) * (T * G);
+        for (int r = 0; r < lim; r += T * G) {
             float m1[R], m2[R];
 #pragma unroll
             for (int h = 0; h < G; ++h) {

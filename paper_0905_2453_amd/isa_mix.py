@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import functools
 import hashlib
 import json
 import os
@@ -32,6 +33,7 @@ CLASSES = {
 }
 
 
+@functools.lru_cache(maxsize=4)
 def _asm(path: str) -> str:
     out = os.path.join(tempfile.mkdtemp(), "direct.s")
     flags = [f for f in B.FLAGS if f != "-fPIC"]

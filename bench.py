@@ -143,18 +143,21 @@ def workload(name):
     return synth.workload_paper()
 
 
-def cpu_baseline(w, n_rays: int, gpu_pix=None):
+def cpu_baseline(w, n_rays: int, gpu_pix=None, gpu_y=None):
     """The FP64 oracle on a bounded sample of the same workload (n_rays rays drawn with the counter
     hash: by default the 2^22 of the paper-scale parity test, about 30 s on 16 host threads), timed
     on the host threads; with the GPU's per-ray pixels of the whole grid (gpu_pix) the same sample
-    gives the counted pixel-switch fraction of the benchmark's own launch."""
+    gives the counted pixel-switch fraction of the benchmark's own launch, and with its per-ray
+    source positions (gpu_y) the expected fraction: a ray whose position is off by (d1, d2) changes
+    pixel with probability d1 / pixel1 + d2 / pixel2 when sources are spread evenly over a pixel, so
+    the mean of that over the sample estimates the fraction without the counting noise."""
     import math
     import oracle
     import synth
     threads = max(1, min(16, os.cpu_count() or 1))
     idx = synth.sample_indices(12, w.n_rays, max(1, min(w.n_rays, n_rays)))
     t0 = time.perf_counter()
-    _, p_o = oracle.trace_parallel(w, idx, threads=threads)
+    y_o, p_o = oracle.trace_parallel(w, idx, threads=threads)
     dt = time.perf_counter() - t0
     inter = len(idx) * w.n_lens
     base = {"value": inter / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
@@ -170,6 +173,11 @@ def cpu_baseline(w, n_rays: int, gpu_pix=None):
                   "switch_fraction": diff / max(1, inmap), "bar": 1e-5,
                   "switches_allowed": 1e-5 * inmap + 3.0 * math.sqrt(1e-5 * inmap),
                   "reference": "FP64 oracle, same rays, pixel or lost outcome per ray"}
+        if gpu_y is not None:
+            ok = np.isfinite(y_o).all(1) & (p_o >= 0)
+            d = np.abs(gpu_y[idx][ok] - y_o[ok])
+            px = [(w.map_hi[k] - w.map_lo[k]) / w.map_n[k] for k in (0, 1)]
+            parity["switch_fraction_expected"] = float(np.mean(d[:, 0] / px[0] + d[:, 1] / px[1]))
     return base, parity
 
 
@@ -694,8 +702,9 @@ def main():
         P.shoot_job(job, ws, dopts, stream)
         torch.cuda.synchronize()
         pix = rp.cpu().numpy()
+        ray_y = ry.cpu().numpy()
         del ry, rp
-        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_rays, pix)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(w, args.cpu_rays, pix, ray_y)
     print(json.dumps(out), flush=True)
 
 
